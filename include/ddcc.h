@@ -1,0 +1,176 @@
+/*
+ * ddcc.h - C ABI of the MI355X DD-CCLB library (libddcc.so).
+ *
+ * The library advances the diffuse-domain consistent and conservative
+ * lattice Boltzmann scheme of Liu, Zhan, Chen, Chai and Shi (arXiv
+ * 2311.10314), Section 3: N phase-field distribution sets f^i (eq. 3.1) and
+ * one flow set g (eq. 3.2), Hermite-moment collision Lambda = H^-1 S H
+ * (eqs. 3.3-3.4), diffuse-domain and wetting sources from the smooth
+ * characteristic function psi (eq. 2.14, eqs. 3.5-3.13), pull streaming, and
+ * recovery of C_i, u and P (moment recovery of Section 3, eq. 19).
+ *
+ * Units are lattice units: dx = dt = c = 1, c_s^2 = d0 (Section 3).
+ * Grids are periodic boxes; walls are embedded through psi (Section 2.3).
+ *
+ * Array layout of every field crossing this ABI: C order, x fastest:
+ *   scalar field  [nz][ny][nx]            (nz = 1 in 2D)
+ *   per-phase     [nphase][nz][ny][nx]
+ *   vector        [dim][nz][ny][nx]       (component 0 = x, 1 = y, 2 = z)
+ * Host arrays are float64. The *_dev variants take device pointers to
+ * float64 arrays of the same layout (e.g. torch tensors on the GPU) and work
+ * on the context's stream without a host copy.
+ *
+ * Ownership: the caller owns every array it passes. The library copies
+ * inputs in during the call (host variants) or enqueues the copy on its stream
+ * (device variants: keep the memory alive until ddcc_sync returns). The
+ * context owns all of its device memory and releases it in ddcc_destroy.
+ *
+ * Errors: every call returns DDCC_OK (0) or one of the DDCC_E_* codes; no C++
+ * exception crosses the ABI. ddcc_last_error() gives a message for the last
+ * failed call on that context. A context stays valid for ddcc_destroy after
+ * any error.
+ */
+#ifndef DDCC_H
+#define DDCC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DDCC_OK 0
+#define DDCC_E_INVAL 1       /* bad shape, parameter or non-finite input      */
+#define DDCC_E_STATE 2       /* call out of order (step before both inits)     */
+#define DDCC_E_NOMEM 3       /* device allocation failed                       */
+#define DDCC_E_HIP 4         /* HIP runtime error; text in ddcc_last_error     */
+#define DDCC_E_NONFINITE 5   /* a diagnostic found NaN/Inf in the populations */
+#define DDCC_E_UNSUPPORTED 6 /* valid input this build has no kernel for      */
+
+/* Velocity sets (Section 3 tables; D3Q19 weights from the same moment
+ * constraints). */
+#define DDCC_D2Q9 0
+#define DDCC_D3Q7 1
+#define DDCC_D3Q15 2
+#define DDCC_D3Q19 3
+
+/* Storage / arithmetic precision of the populations and history. */
+#define DDCC_FP64 0  /* float64 storage, float64 arithmetic              */
+#define DDCC_FP32 1  /* float32 storage, float32 arithmetic              */
+
+#define DDCC_MAX_PHASES 4
+
+/* Rate slots of s_f[] and s_g[]: the diagonal of S (Section 3 lattice
+ * tables): s0, s1, s21, s22, s3, s4. For the flow set s_g[2] and s_g[3] are
+ * ignored: s21 and s22 follow the local viscosity through eq. (16). */
+#define DDCC_S0 0
+#define DDCC_S1 1
+#define DDCC_S21 2
+#define DDCC_S22 3
+#define DDCC_S3 4
+#define DDCC_S4 5
+
+typedef struct ddcc_params {
+  int dim;          /* 2 or 3                                               */
+  int nx, ny, nz;   /* grid size; nz = 1 when dim = 2; all >= 1             */
+  int nphase;       /* N, 2 <= N <= DDCC_MAX_PHASES                          */
+  int lattice_f;    /* velocity set of the phase sets (DDCC_D2Q9 / D3Q15)    */
+  int lattice_g;    /* velocity set of the flow set   (DDCC_D2Q9 / D3Q19)    */
+  int precision;    /* DDCC_FP64 or DDCC_FP32                                */
+  double d0;        /* c_s^2 / c^2, inside the lattices' positive-weight range */
+  double eps;       /* fluid-fluid interface width (cells), Section 2.1       */
+  double m0;        /* mobility of eq. (2.5)                                  */
+  double rho0;      /* constant of g^eq_0, eq. (3.8)                          */
+  double psi_min;   /* floor of psi in the divisions phi X / phi (> 0)        */
+  double lam;       /* penalty coefficient of (1 - psi) u, eq. (2.13c) (>= 0) */
+  double sigma[DDCC_MAX_PHASES][DDCC_MAX_PHASES]; /* symmetric, zero diagonal,
+                                                     > 0 off the diagonal     */
+  double rho[DDCC_MAX_PHASES];  /* phase densities (> 0)                      */
+  double nu[DDCC_MAX_PHASES];   /* phase kinematic viscosities (> 0)          */
+  double eta[DDCC_MAX_PHASES];  /* eta_i of eq. (3.5); <= 0 means derive it
+                                   from m0 and s_f[1] by eq. (17)            */
+  double s_f[6];    /* rates of the phase sets, each in (0, 2)               */
+  double s_g[6];    /* rates of the flow set (slots 2, 3 unused)             */
+  double accel[3];  /* body acceleration; adds psi rho a to the force        */
+} ddcc_params;
+
+typedef struct ddcc_ctx ddcc_ctx;
+
+/* Fills *p with defaults: the lattice and rate choices of Section 4
+ * (s_f = {1, 10/19, 1.2, 1.2, 1.2, 1.2}, s_g = {1, 1.2, -, -, 1.2, 1.2}),
+ * d0 = 0.4, eps = 5, m0 = 0.05, rho0 = 1, psi_min = 1e-30, sigma_ij = 0.001,
+ * rho = nu-independent 1, nu = 0.1, derived eta, no body force, for a 2D
+ * D2Q9 N = 2 FP64 box of 64 x 64. Always returns DDCC_OK for p != NULL. */
+int ddcc_default_params(ddcc_params* p);
+
+/* Validates *p and allocates the device state on the current HIP device.
+ * `stream` is a hipStream_t to run on (e.g. a torch stream), or NULL for a
+ * stream the context creates and owns. On success *out holds a new context;
+ * on failure *out is NULL and the return code says why. */
+int ddcc_create(const ddcc_params* p, void* stream, ddcc_ctx** out);
+
+/* Static geometry (eq. 2.14 and Section 2.3): psi [nz][ny][nx] in [0, 1]
+ * and cos_theta [N-1][nz][ny][nx]: cos of the contact angle theta_iN of
+ * phase i against phase N, measured inside phase i (eqs. 2.7-2.9), each in
+ * [-1, 1]; NULL means 90 degrees everywhere. Must precede ddcc_init_fields. */
+int ddcc_init_geometry(ddcc_ctx* ctx, const double* psi,
+                       const double* cos_theta);
+int ddcc_init_geometry_dev(ddcc_ctx* ctx, const double* psi_dev,
+                           const double* cos_theta_dev);
+
+/* Initial state: C [N][nz][ny][nx] (volume fractions), u [dim][..] or NULL
+ * for rest, P [..] or NULL for zero. Populations start at their equilibria
+ * (eqs. 3.5, 3.8) and every time derivative starts at zero. Resets time. */
+int ddcc_init_fields(ddcc_ctx* ctx, const double* C, const double* u,
+                     const double* P);
+int ddcc_init_fields_dev(ddcc_ctx* ctx, const double* C_dev,
+                         const double* u_dev, const double* P_dev);
+
+/* Advances nsteps >= 0 time steps (eqs. 3.1, 3.2), asynchronously on the
+ * context stream (one fused kernel per step). */
+int ddcc_step(ddcc_ctx* ctx, int64_t nsteps);
+
+/* C_i, u and P of the current time level (moment recovery of Section 3 and
+ * eq. 19); any pointer may be NULL to skip that field. Host variant
+ * synchronises the stream; device variant only enqueues. */
+int ddcc_read_moments(ddcc_ctx* ctx, double* C, double* u, double* P);
+int ddcc_read_moments_dev(ddcc_ctx* ctx, double* C_dev, double* u_dev,
+                          double* P_dev);
+
+/* Per-phase mass sum_x sum_p f^i_p in float64 (conserved exactly by the
+ * scheme: sum_p F^i_p = 0 and sum_p f^i,eq_p = phi C_i). Synchronises.
+ * Returns DDCC_E_NONFINITE if any population is NaN or Inf. */
+int ddcc_mass(ddcc_ctx* ctx, double* mass /* [nphase] */);
+
+/* Number of completed steps since ddcc_init_fields. */
+int64_t ddcc_time(const ddcc_ctx* ctx);
+
+/* Exact checkpoint of populations and history. With buf == NULL, *bytes
+ * receives the size needed; otherwise *bytes must be at least that size and
+ * the state is copied to host memory `buf`. Synchronises. */
+int ddcc_save(ddcc_ctx* ctx, void* buf, size_t* bytes);
+/* Restores a checkpoint written by ddcc_save for identical ddcc_params. */
+int ddcc_load(ddcc_ctx* ctx, const void* buf, size_t bytes);
+
+/* Waits for all work queued on the context stream. */
+int ddcc_sync(ddcc_ctx* ctx);
+
+/* Kernel launch shape of the step kernel: tile (tx, ty) of nodes per
+ * workgroup; 0 keeps the default. Takes effect on the next ddcc_step. */
+int ddcc_set_tile(ddcc_ctx* ctx, int tx, int ty);
+
+/* Message of the last failed call on ctx (never NULL; "" if none). */
+const char* ddcc_last_error(const ddcc_ctx* ctx);
+
+/* Releases the context and its device memory; NULL is a no-op. */
+void ddcc_destroy(ddcc_ctx* ctx);
+
+/* Library version string. */
+const char* ddcc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DDCC_H */

@@ -1,0 +1,610 @@
+// Fused 2D DD-CCLB step for gfx950 (D2Q9 phase and flow sets).
+//
+// One workgroup owns a TX x TY tile of nodes (TX = 64: one wavefront per
+// row, so every global access of a row is one coalesced 64-wide load).
+// Per step and node (Section 3, in order):
+//   phase 1  pull f^i from buffer A and sum: phi C_i, C_i = phi C_i / psi_hat
+//            on the tile plus a 2-node halo, into LDS with psi and phi rho;
+//   phase 2  chemical potential phi mu_i (eq. 2.14) on the tile plus a
+//            1-node halo (needs div(psi grad C_j) and |grad psi| from LDS),
+//            mu_i = phi mu_i / psi_hat into LDS, and the lagged flux tensor T;
+//   phase 3  own node: gradients from LDS, mobility terms (eqs. 2.5, 3.7),
+//            force and velocity (eq. 3.13 with the implicit penalty),
+//            pressure (eq. 19), equilibria and sources (eqs. 3.5-3.12),
+//            Hermite-moment collision (eqs. 3.1-3.4) in registers, and the
+//            post-collision populations written to buffer B at the node
+//            (pull streaming: the next step reads them at x - c_p).
+// The same kernel body also serves initialisation (populations at
+// equilibrium) and moment read-out, selected by a template parameter.
+//
+// Storage S (float/double), arithmetic R (float/double). The rest population
+// of the flow set is stored as g_0 - rho0 (small), every other population
+// raw. History per node: phi C_i u (N x 2), the symmetric flux tensor Y
+// (xx, xy, yy) and P, updated in place; the antisymmetric tensor T (xy) is
+// double-buffered because neighbours read it.
+#include <hip/hip_runtime.h>
+
+#include "coef.hpp"
+#include "kernels.hpp"
+#include "lattice.hpp"
+
+namespace ddcc {
+
+namespace {
+
+constexpr int TX = 64;
+
+template <class R>
+__device__ inline R gprime(R C) {
+  // g(C) = C^2 (C - 1)^2  =>  g'(C) = 2 C (C - 1)(2 C - 1)   (Section 2.1)
+  return R(2) * C * (C - R(1)) * (R(2) * C - R(1));
+}
+
+__device__ inline int wrap(int v, int n) {
+  int m = v % n;
+  return m < 0 ? m + n : m;
+}
+
+// Fixed isotropic finite-difference stencil (D2Q9 weights at d0 = 1/3
+// divided by its c_s^2 = 1/3): 1/3 on the axes, 1/12 on the diagonals.
+// Neighbour order in the 3x3 patch arrays: [dy+1][dx+1].
+template <class R>
+struct Patch {
+  R v[3][3];
+};
+
+template <class R>
+__device__ inline R grad_x(const Patch<R>& p) {
+  return R(1.0 / 3.0) * (p.v[1][2] - p.v[1][0]) +
+         R(1.0 / 12.0) * ((p.v[2][2] + p.v[0][2]) - (p.v[2][0] + p.v[0][0]));
+}
+
+template <class R>
+__device__ inline R grad_y(const Patch<R>& p) {
+  return R(1.0 / 3.0) * (p.v[2][1] - p.v[0][1]) +
+         R(1.0 / 12.0) * ((p.v[2][2] + p.v[2][0]) - (p.v[0][2] + p.v[0][0]));
+}
+
+// div(psi grad C) in conservative two-point-flux form.
+template <class R>
+__device__ inline R div_psi_grad(const Patch<R>& psi, const Patch<R>& C) {
+  const R pc = psi.v[1][1], cc = C.v[1][1];
+  R axis = (psi.v[1][2] + pc) * (C.v[1][2] - cc) +
+           (psi.v[1][0] + pc) * (C.v[1][0] - cc) +
+           (psi.v[2][1] + pc) * (C.v[2][1] - cc) +
+           (psi.v[0][1] + pc) * (C.v[0][1] - cc);
+  R diag = (psi.v[2][2] + pc) * (C.v[2][2] - cc) +
+           (psi.v[2][0] + pc) * (C.v[2][0] - cc) +
+           (psi.v[0][2] + pc) * (C.v[0][2] - cc) +
+           (psi.v[0][0] + pc) * (C.v[0][0] - cc);
+  return R(1.0 / 3.0) * axis + R(1.0 / 12.0) * diag;
+}
+
+template <class R, int W, int H>
+__device__ inline Patch<R> patch(const R (&a)[H][W], int x, int y) {
+  Patch<R> p;
+#pragma unroll
+  for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+    for (int dx = -1; dx <= 1; ++dx) p.v[dy + 1][dx + 1] = a[y + dy][x + dx];
+  return p;
+}
+
+template <class S, class R>
+__device__ inline R ld(const S* p) {
+  return static_cast<R>(*p);
+}
+
+// Pull: population p at (gx, gy) comes from (gx - c_px, gy - c_py).
+struct Nbr {
+  int xm, xp, ym, yp, x, y, nx;
+  __device__ inline int src(int cx, int cy) const {
+    const int sx = cx == 1 ? xm : (cx == -1 ? xp : x);
+    const int sy = cy == 1 ? ym : (cy == -1 ? yp : y);
+    return sy * nx + sx;
+  }
+};
+
+__device__ inline Nbr make_nbr(int gx, int gy, int nx, int ny) {
+  Nbr b;
+  b.x = gx;
+  b.y = gy;
+  b.nx = nx;
+  b.xm = gx == 0 ? nx - 1 : gx - 1;
+  b.xp = gx == nx - 1 ? 0 : gx + 1;
+  b.ym = gy == 0 ? ny - 1 : gy - 1;
+  b.yp = gy == ny - 1 ? 0 : gy + 1;
+  return b;
+}
+
+template <int N, class S, class R, int MODE, int TY>
+struct Step2D {
+  static constexpr int Q = 9;
+  static constexpr int NT = TX * TY;
+  static constexpr int HX = TX + 4, HY = TY + 4;  // C region (halo 2)
+  static constexpr int MX = TX + 2, MY = TY + 2;  // mu region (halo 1)
+  static constexpr int RING1 = HX * HY - TX * TY;
+  static constexpr int RING2 = MX * MY - TX * TY;
+
+  struct Smem {
+    R psi[HY][HX];
+    R prho[HY][HX];
+    R C[N][HY][HX];
+    R mu[N][MY][MX];
+    R T[MY][MX];
+  };
+
+  __device__ static inline void ring1(int r, int& lx, int& ly) {
+    if (r < 2 * HX) {
+      ly = r / HX;
+      lx = r - ly * HX;
+    } else if (r < 4 * HX) {
+      const int q = r - 2 * HX;
+      ly = HY - 2 + q / HX;
+      lx = q - (q / HX) * HX;
+    } else {
+      const int q = r - 4 * HX;
+      ly = 2 + (q >> 2);
+      const int c = q & 3;
+      lx = c < 2 ? c : HX - 4 + c;
+    }
+  }
+
+  __device__ static inline void ring2(int r, int& mx, int& my) {
+    if (r < MX) {
+      my = 0;
+      mx = r;
+    } else if (r < 2 * MX) {
+      my = MY - 1;
+      mx = r - MX;
+    } else {
+      const int q = r - 2 * MX;
+      my = 1 + (q >> 1);
+      mx = (q & 1) ? MX - 1 : 0;
+    }
+  }
+
+  // Phase 1 at C-region coordinates (lx, ly).
+  __device__ static inline void node1(Smem& sm, const Coef<R>& k,
+                                      const Bufs<S>& b, int x0, int y0, int lx,
+                                      int ly, R* psiC_out) {
+    const int gx = wrap(x0 + lx - 2, k.nx), gy = wrap(y0 + ly - 2, k.ny);
+    const long long idx = (long long)gy * k.nx + gx;
+    const R psi = ld<S, R>(b.psi + idx);
+    R rho = R(0);
+    if constexpr (MODE == MODE_INIT) {
+#pragma unroll
+      for (int i = 0; i < N; ++i)
+        psiC_out[i] = psi * R(b.inC[i * k.n + idx]);
+    } else {
+      const Nbr nb = make_nbr(gx, gy, k.nx, k.ny);
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        const S* f = b.fA + (long long)i * Q * k.n;
+        R s = R(0);
+#pragma unroll
+        for (int p = 0; p < Q; ++p)
+          s += ld<S, R>(f + p * k.n + nb.src(D2Q9::c[p].x, D2Q9::c[p].y));
+        psiC_out[i] = s;
+      }
+    }
+    // C_i = phi C_i / sum_j phi C_j: equal to phi C_i / phi while the
+    // constraint sum_j C_j = 1 of Section 2.1 holds, and keeps it exact.
+    R tot = R(0);
+#pragma unroll
+    for (int i = 0; i < N; ++i) tot += psiC_out[i];
+    const R inv = R(1) / (tot > k.psi_min ? tot : k.psi_min);
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      const R C = psiC_out[i] * inv;
+      sm.C[i][ly][lx] = C;
+      rho += k.rho[i] * C;
+    }
+    sm.psi[ly][lx] = psi;
+    sm.prho[ly][lx] = psi * rho;
+  }
+
+  // Phase 2 at mu-region coordinates (mx, my): phi mu_i (eq. 2.14).
+  __device__ static inline void node2(Smem& sm, const Coef<R>& k,
+                                      const Bufs<S>& b, int x0, int y0, int mx,
+                                      int my, R* psimu_out) {
+    const int lx = mx + 1, ly = my + 1;
+    const int gx = wrap(x0 + mx - 1, k.nx), gy = wrap(y0 + my - 1, k.ny);
+    const long long idx = (long long)gy * k.nx + gx;
+    const Patch<R> ps = patch(sm.psi, lx, ly);
+    const R psi = ps.v[1][1];
+    const R psih = psi > k.psi_min ? psi : k.psi_min;
+    const R gpx = grad_x(ps), gpy = grad_y(ps);
+    const R agp = sqrt(gpx * gpx + gpy * gpy);
+    R C[N], L[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      const Patch<R> cp = patch(sm.C[j], lx, ly);
+      C[j] = cp.v[1][1];
+      L[j] = div_psi_grad(ps, cp);
+    }
+    // cos theta_jq from the N-1 stored cos theta_iN (eq. 2.9)
+    R ct[N];
+#pragma unroll
+    for (int i = 0; i < N - 1; ++i) ct[i] = ld<S, R>(b.ct + i * k.n + idx);
+    ct[N - 1] = R(0);
+    R W[N];  // sum_{q != j} cos theta_jq C_j C_q
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      R acc = R(0);
+#pragma unroll
+      for (int q = 0; q < N; ++q)
+        if (q != j) {
+          const R cjq = (k.sigN[j] * ct[j] - k.sigN[q] * ct[q]) * k.inv_sig[j][q];
+          acc += cjq * C[j] * C[q];
+        }
+      W[j] = acc;
+    }
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      R bulk = R(0), grad = R(0), wet = R(0);
+      const R gi = gprime(C[i]);
+#pragma unroll
+      for (int j = 0; j < N; ++j) {
+        if (j != i) {
+          bulk += k.beta2[i][j] * (gi - gprime(C[i] + C[j]));
+          grad += k.grad34[i][j] * L[j];
+          wet += k.wet3[i][j] * W[j];
+        }
+      }
+      const R pm = psi * bulk + grad + wet * agp;
+      psimu_out[i] = pm;
+      sm.mu[i][my][mx] = pm / psih;
+    }
+    if constexpr (MODE != MODE_INIT) sm.T[my][mx] = ld<S, R>(b.TA + idx);
+  }
+
+  __device__ static void run(const Coef<R>& k, const Bufs<S>& b) {
+    __shared__ Smem sm;
+    const int tid = threadIdx.x;
+    const int tx = tid % TX, ty = tid / TX;
+    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
+
+    R psiC[N], psimu[N], dummy[N];
+    node1(sm, k, b, x0, y0, tx + 2, ty + 2, psiC);
+    for (int r = tid; r < RING1; r += NT) {
+      int lx, ly;
+      ring1(r, lx, ly);
+      node1(sm, k, b, x0, y0, lx, ly, dummy);
+    }
+    __syncthreads();
+    node2(sm, k, b, x0, y0, tx + 1, ty + 1, psimu);
+    for (int r = tid; r < RING2; r += NT) {
+      int mx, my;
+      ring2(r, mx, my);
+      node2(sm, k, b, x0, y0, mx, my, dummy);
+    }
+    __syncthreads();
+
+    const int gx = x0 + tx, gy = y0 + ty;
+    if (gx >= k.nx || gy >= k.ny) return;
+    const long long n = k.n;
+    const long long idx = (long long)gy * k.nx + gx;
+    const int lx = tx + 2, ly = ty + 2, mx = tx + 1, my = ty + 1;
+
+    // ---- gradients from LDS -------------------------------------------
+    const Patch<R> ps = patch(sm.psi, lx, ly);
+    const R psi = ps.v[1][1];
+    const R psih = psi > k.psi_min ? psi : k.psi_min;
+    const R gpsi[2] = {grad_x(ps), grad_y(ps)};
+    const Patch<R> pr = patch(sm.prho, lx, ly);
+    const R psirho = pr.v[1][1];
+    const R gprho[2] = {grad_x(pr), grad_y(pr)};
+    R C[N], gC[N][2], mu[N], gmu[N][2];
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      const Patch<R> cp = patch(sm.C[i], lx, ly);
+      C[i] = cp.v[1][1];
+      gC[i][0] = grad_x(cp);
+      gC[i][1] = grad_y(cp);
+      const Patch<R> mp = patch(sm.mu[i], mx, my);
+      mu[i] = mp.v[1][1];
+      gmu[i][0] = grad_x(mp);
+      gmu[i][1] = grad_y(mp);
+    }
+    R grho[2] = {R(0), R(0)};
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      grho[0] += k.rho[i] * gC[i][0];
+      grho[1] += k.rho[i] * gC[i][1];
+    }
+    // mass flux m^C = -sum_ij rho_i M_ij grad mu_j, with
+    // sum_i rho_i M_ij = m0 C_j sum_{k != j} C_k (rho_j - rho_k)  (eq. 2.5)
+    R mC[2] = {R(0), R(0)};
+    R Cs[N];  // sum_{k != j} C_k
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      R s = R(0), sr = R(0);
+#pragma unroll
+      for (int q = 0; q < N; ++q)
+        if (q != j) {
+          s += C[q];
+          sr += C[q] * (k.rho[j] - k.rho[q]);
+        }
+      Cs[j] = s;
+      const R a = k.m0 * C[j] * sr;
+      mC[0] -= a * gmu[j][0];
+      mC[1] -= a * gmu[j][1];
+    }
+
+    R u[2], F[2] = {R(0), R(0)};
+    R gp[Q];
+    R sum_gm = R(0);
+    const Nbr nb = make_nbr(gx, gy, k.nx, k.ny);
+    if constexpr (MODE == MODE_INIT) {
+      u[0] = b.inU ? R(b.inU[idx]) : R(0);
+      u[1] = b.inU ? R(b.inU[n + idx]) : R(0);
+    } else {
+      R j[2] = {R(0), R(0)};
+#pragma unroll
+      for (int p = 0; p < Q; ++p) {
+        gp[p] = ld<S, R>(b.gA + p * n + nb.src(D2Q9::c[p].x, D2Q9::c[p].y));
+        if (p > 0) sum_gm += gp[p];
+        if (D2Q9::c[p].x) j[0] += R(D2Q9::c[p].x) * gp[p];
+        if (D2Q9::c[p].y) j[1] += R(D2Q9::c[p].y) * gp[p];
+      }
+      // force (eq. 3.13): -div T^{n-1} + sum_i phi mu_i grad C_i
+      //                   + P^{n-1} grad psi + psi rho a
+      const Patch<R> tp = patch(sm.T, mx, my);
+      const R Pprev = ld<S, R>(b.hist + (2 * N + 3) * n + idx);
+      R Fp[2];
+      Fp[0] = grad_y(tp) + Pprev * gpsi[0] + psirho * k.accel[0];
+      Fp[1] = -grad_x(tp) + Pprev * gpsi[1] + psirho * k.accel[1];
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        Fp[0] += psimu[i] * gC[i][0];
+        Fp[1] += psimu[i] * gC[i][1];
+      }
+      // phi rho u = j + F/2 with F = Fp - (1 - psi) lam u, solved for u
+      const R pen = (R(1) - psi) * k.lam;
+      const R den = R(1) / (psirho + R(0.5) * pen);
+      u[0] = (j[0] + R(0.5) * Fp[0]) * den;
+      u[1] = (j[1] + R(0.5) * Fp[1]) * den;
+      F[0] = Fp[0] - pen * u[0];
+      F[1] = Fp[1] - pen * u[1];
+    }
+
+    // symmetric / antisymmetric flux tensors of phi m^C u
+    const R Y[3] = {psi * mC[0] * u[0],
+                    R(0.5) * psi * (mC[0] * u[1] + u[0] * mC[1]),
+                    psi * mC[1] * u[1]};
+    const R Tn = R(0.5) * psi * (mC[0] * u[1] - u[0] * mC[1]);
+    R dtY[3] = {R(0), R(0), R(0)};
+    if constexpr (MODE != MODE_INIT) {
+#pragma unroll
+      for (int q = 0; q < 3; ++q)
+        dtY[q] = Y[q] - ld<S, R>(b.hist + (2 * N + q) * n + idx);
+    }
+
+    // local flow rates from nu (eq. 16)
+    R nu = R(0);
+#pragma unroll
+    for (int i = 0; i < N; ++i) nu += k.nu[i] * C[i];
+    const R s21 = R(1) / (k.two_over_c2mcs2 * nu + R(0.5));
+    const R s22 = R(1) / (k.inv_cs2 * nu + R(0.5));
+
+    R psiP, P;
+    const R A[3] = {psirho * u[0] * u[0] + Y[0], psirho * u[0] * u[1] + Y[1],
+                    psirho * u[1] * u[1] + Y[2]};
+    if constexpr (MODE == MODE_INIT) {
+      P = b.inP ? R(b.inP[idx]) : R(0);
+      psiP = psi * P;
+    } else {
+      // eq. (19)
+      const R s0eq = -k.wg[0] * (A[0] + A[2]) * k.inv_c2mcs2;
+      const R ugr = u[0] * grho[0] + u[1] * grho[1];
+      const R ugpr = u[0] * gprho[0] + u[1] * gprho[1];
+      psiP = k.pref * (sum_gm + k.cgr * psi * ugr + k.halfK * (dtY[0] + dtY[2]) +
+                       k.KH * (s21 - R(2)) / s21 * ugpr + s0eq);
+      P = psiP / psih;
+    }
+
+    if constexpr (MODE == MODE_MOMENTS) {
+#pragma unroll
+      for (int i = 0; i < N; ++i) b.outC[i * n + idx] = double(C[i]);
+      b.outU[idx] = double(u[0]);
+      b.outU[n + idx] = double(u[1]);
+      b.outP[idx] = double(P);
+      return;
+    }
+
+    // ---- flow set: equilibrium (eqs. 3.8, 3.11), source (3.10, 3.12) ---
+    {
+      R d[Q], G[Q];
+#pragma unroll
+      for (int p = 0; p < Q; ++p) {
+        const int cx = D2Q9::c[p].x, cy = D2Q9::c[p].y;
+        const R h2 = (A[0] * (R(cx * cx) - k.cs2) + A[2] * (R(cy * cy) - k.cs2)) *
+                         k.h2diag +
+                     A[1] * R(cx * cy) * k.h2off;
+        R geq = k.wg[p] * ((psiP + R(cx) * psirho * u[0] + R(cy) * psirho * u[1]) *
+                               k.inv_cs2 + h2);
+        if (p == 0) geq -= psiP * k.inv_cs2;  // stored as g_0 - rho0
+        if constexpr (MODE == MODE_INIT) {
+          d[p] = geq;
+        } else {
+          d[p] = gp[p] - geq;
+        }
+      }
+      if constexpr (MODE == MODE_INIT) {
+        // the buffers hold pre-streaming values: place g_p(x) where the next
+        // pull reads it, at x - c_p
+#pragma unroll
+        for (int p = 0; p < Q; ++p)
+          b.gB[p * n + nb.src(D2Q9::c[p].x, D2Q9::c[p].y)] = S(d[p]);
+      } else {
+        const R ub = u[0] * gprho[0] + u[1] * gprho[1];
+        const R M[3] = {dtY[0] + R(2) * k.cs2 * u[0] * gprho[0] + k.one_m3cs2 * ub,
+                        dtY[1] + k.cs2 * (u[0] * gprho[1] + gprho[0] * u[1]),
+                        dtY[2] + R(2) * k.cs2 * u[1] * gprho[1] + k.one_m3cs2 * ub};
+        const R a0 = psi * (u[0] * grho[0] + u[1] * grho[1]);
+#pragma unroll
+        for (int p = 0; p < Q; ++p) {
+          const int cx = D2Q9::c[p].x, cy = D2Q9::c[p].y;
+          const R h2 = (M[0] * (R(cx * cx) - k.cs2) + M[2] * (R(cy * cy) - k.cs2)) *
+                           k.h2diag +
+                       M[1] * R(cx * cy) * k.h2off;
+          G[p] = k.wg[p] * (a0 + (R(cx) * F[0] + R(cy) * F[1]) * k.inv_cs2 + h2);
+        }
+        R m[Q], mg[Q], ms[Q], del[Q];
+        to_hermite<D2Q9>(d, m, k.cs2);
+        to_hermite<D2Q9>(G, mg, k.cs2);
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+          const int grp = D2Q9::rows[q].group;
+          const R s = grp == GR21 ? s21 : (grp == GR22 ? s22 : k.sg[grp]);
+          ms[q] = s * m[q] - (R(1) - R(0.5) * s) * mg[q];
+        }
+        from_hermite<D2Q9>(ms, del, k.cs2);
+#pragma unroll
+        for (int p = 0; p < Q; ++p) b.gB[p * n + idx] = S(gp[p] - del[p]);
+      }
+    }
+
+    // ---- phase sets: equilibrium (3.5), source (3.6, 3.7), collision ---
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      const R X[2] = {psiC[i] * u[0], psiC[i] * u[1]};
+      R V[2] = {R(0), R(0)};
+      if constexpr (MODE != MODE_INIT) {
+        // S_i = psi [(C_i sum_{j!=i} C_j - 1) grad mu_i
+        //            - C_i sum_{j != i} C_j grad mu_j]
+        R Sx = (C[i] * Cs[i] - R(1)) * gmu[i][0];
+        R Sy = (C[i] * Cs[i] - R(1)) * gmu[i][1];
+#pragma unroll
+        for (int j = 0; j < N; ++j)
+          if (j != i) {
+            Sx -= C[i] * C[j] * gmu[j][0];
+            Sy -= C[i] * C[j] * gmu[j][1];
+          }
+        Sx *= psi;
+        Sy *= psi;
+        const R dX0 = X[0] - ld<S, R>(b.hist + (2 * i) * n + idx);
+        const R dX1 = X[1] - ld<S, R>(b.hist + (2 * i + 1) * n + idx);
+        V[0] = dX0 + k.cs2 * k.eta[i] * (mu[i] * gpsi[0] - Sx);
+        V[1] = dX1 + k.cs2 * k.eta[i] * (mu[i] * gpsi[1] - Sy);
+      }
+      const R em = k.eta[i] * psimu[i];
+      R d[Q];
+      const S* fsrc = b.fA + (long long)i * Q * n;
+      S* fdst = b.fB + (long long)i * Q * n;
+      R fp[Q];
+#pragma unroll
+      for (int p = 0; p < Q; ++p) {
+        const int cx = D2Q9::c[p].x, cy = D2Q9::c[p].y;
+        R feq = k.wf[p] * (em + (R(cx) * X[0] + R(cy) * X[1]) * k.inv_cs2);
+        if (p == 0) feq = (k.wf[0] - R(1)) * em + psiC[i];
+        if constexpr (MODE == MODE_INIT) {
+          d[p] = feq;
+        } else {
+          fp[p] = ld<S, R>(fsrc + p * n + nb.src(cx, cy));
+          d[p] = fp[p] - feq;
+        }
+      }
+      if constexpr (MODE == MODE_INIT) {
+#pragma unroll
+        for (int p = 0; p < Q; ++p)
+          fdst[p * n + nb.src(D2Q9::c[p].x, D2Q9::c[p].y)] = S(d[p]);
+      } else {
+        R Fs[Q];
+#pragma unroll
+        for (int p = 0; p < Q; ++p) {
+          const int cx = D2Q9::c[p].x, cy = D2Q9::c[p].y;
+          Fs[p] = k.wf[p] * (R(cx) * V[0] + R(cy) * V[1]) * k.inv_cs2;
+        }
+        R m[Q], mf[Q], ms[Q], del[Q];
+        to_hermite<D2Q9>(d, m, k.cs2);
+        to_hermite<D2Q9>(Fs, mf, k.cs2);
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+          const R s = k.sf[D2Q9::rows[q].group];
+          ms[q] = s * m[q] - (R(1) - R(0.5) * s) * mf[q];
+        }
+        from_hermite<D2Q9>(ms, del, k.cs2);
+#pragma unroll
+        for (int p = 0; p < Q; ++p) fdst[p * n + idx] = S(fp[p] - del[p]);
+      }
+      b.hist[(2 * i) * n + idx] = S(X[0]);
+      b.hist[(2 * i + 1) * n + idx] = S(X[1]);
+    }
+#pragma unroll
+    for (int q = 0; q < 3; ++q) b.hist[(2 * N + q) * n + idx] = S(Y[q]);
+    b.hist[(2 * N + 3) * n + idx] = S(P);
+    b.TB[idx] = S(Tn);
+  }
+};
+
+template <int N, class S, class R, int MODE, int TY>
+__global__ __launch_bounds__(TX* TY) void k_step2d(Coef<R> k, Bufs<S> b) {
+  Step2D<N, S, R, MODE, TY>::run(k, b);
+}
+
+template <int N, class S, class R, int MODE>
+hipError_t launch_ty(const Coef<R>& k, const Bufs<S>& b, int ty,
+                     hipStream_t st) {
+  switch (ty) {
+    case 4: {
+      dim3 g((k.nx + TX - 1) / TX, (k.ny + 3) / 4);
+      hipLaunchKernelGGL((k_step2d<N, S, R, MODE, 4>), g, dim3(TX * 4), 0, st,
+                         k, b);
+      break;
+    }
+    case 2: {
+      dim3 g((k.nx + TX - 1) / TX, (k.ny + 1) / 2);
+      hipLaunchKernelGGL((k_step2d<N, S, R, MODE, 2>), g, dim3(TX * 2), 0, st,
+                         k, b);
+      break;
+    }
+    default: {
+      dim3 g((k.nx + TX - 1) / TX, (k.ny + 7) / 8);
+      hipLaunchKernelGGL((k_step2d<N, S, R, MODE, 8>), g, dim3(TX * 8), 0, st,
+                         k, b);
+      break;
+    }
+  }
+  return hipGetLastError();
+}
+
+template <int N, class S, class R>
+hipError_t launch_mode(int mode, const Coef<R>& k, const Bufs<S>& b, int ty,
+                       hipStream_t st) {
+  switch (mode) {
+    case MODE_STEP:
+      return launch_ty<N, S, R, MODE_STEP>(k, b, ty, st);
+    case MODE_INIT:
+      return launch_ty<N, S, R, MODE_INIT>(k, b, ty, st);
+    default:
+      return launch_ty<N, S, R, MODE_MOMENTS>(k, b, ty, st);
+  }
+}
+
+}  // namespace
+
+template <class S, class R>
+hipError_t launch_2d(int nphase, int mode, const Coef<R>& k, const Bufs<S>& b,
+                     int ty, hipStream_t st) {
+  switch (nphase) {
+    case 2:
+      return launch_mode<2, S, R>(mode, k, b, ty, st);
+    case 3:
+      return launch_mode<3, S, R>(mode, k, b, ty, st);
+    case 4:
+      return launch_mode<4, S, R>(mode, k, b, ty, st);
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+template hipError_t launch_2d<double, double>(int, int, const Coef<double>&,
+                                              const Bufs<double>&, int,
+                                              hipStream_t);
+template hipError_t launch_2d<float, float>(int, int, const Coef<float>&,
+                                            const Bufs<float>&, int,
+                                            hipStream_t);
+
+}  // namespace ddcc

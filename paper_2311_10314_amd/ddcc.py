@@ -1,0 +1,337 @@
+"""Thin Python binding of libddcc.so (include/ddcc.h).
+
+Argument marshalling only: every step of the scheme runs in the HIP
+library. Importing this module loads the in-tree libddcc.so and raises if it
+is missing; there is no fallback implementation.
+
+The module-level functions carry the C names (ddcc_create, ddcc_step, ...).
+`Sim` wraps one context for convenience: numpy arrays for the host calls,
+torch CUDA tensors (float64, contiguous) for the *_dev calls.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libddcc.so")
+
+DDCC_OK = 0
+DDCC_E_INVAL = 1
+DDCC_E_STATE = 2
+DDCC_E_NOMEM = 3
+DDCC_E_HIP = 4
+DDCC_E_NONFINITE = 5
+DDCC_E_UNSUPPORTED = 6
+
+LATTICES = {"D2Q9": 0, "D3Q7": 1, "D3Q15": 2, "D3Q19": 3}
+FP64, FP32 = 0, 1
+MAX_PHASES = 4
+RATE_SLOTS = ("0", "1", "21", "22", "3", "4")
+
+
+class ddcc_params(ctypes.Structure):
+    _fields_ = [
+        ("dim", ctypes.c_int), ("nx", ctypes.c_int), ("ny", ctypes.c_int),
+        ("nz", ctypes.c_int), ("nphase", ctypes.c_int),
+        ("lattice_f", ctypes.c_int), ("lattice_g", ctypes.c_int),
+        ("precision", ctypes.c_int),
+        ("d0", ctypes.c_double), ("eps", ctypes.c_double),
+        ("m0", ctypes.c_double), ("rho0", ctypes.c_double),
+        ("psi_min", ctypes.c_double), ("lam", ctypes.c_double),
+        ("sigma", (ctypes.c_double * MAX_PHASES) * MAX_PHASES),
+        ("rho", ctypes.c_double * MAX_PHASES),
+        ("nu", ctypes.c_double * MAX_PHASES),
+        ("eta", ctypes.c_double * MAX_PHASES),
+        ("s_f", ctypes.c_double * 6), ("s_g", ctypes.c_double * 6),
+        ("accel", ctypes.c_double * 3),
+    ]
+
+
+class DDCCError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("ddcc error %d: %s" % (code, msg))
+        self.code = code
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            "libddcc.so is not built (%s); run "
+            "`python -m paper_2311_10314_amd.build`" % LIB_PATH)
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER
+    dp = P(ctypes.c_double)
+    vp = ctypes.c_void_p
+    ctx = vp
+    sig = {
+        "ddcc_default_params": (ctypes.c_int, [P(ddcc_params)]),
+        "ddcc_create": (ctypes.c_int, [P(ddcc_params), vp, P(vp)]),
+        "ddcc_init_geometry": (ctypes.c_int, [ctx, dp, dp]),
+        "ddcc_init_geometry_dev": (ctypes.c_int, [ctx, vp, vp]),
+        "ddcc_init_fields": (ctypes.c_int, [ctx, dp, dp, dp]),
+        "ddcc_init_fields_dev": (ctypes.c_int, [ctx, vp, vp, vp]),
+        "ddcc_step": (ctypes.c_int, [ctx, ctypes.c_int64]),
+        "ddcc_read_moments": (ctypes.c_int, [ctx, dp, dp, dp]),
+        "ddcc_read_moments_dev": (ctypes.c_int, [ctx, vp, vp, vp]),
+        "ddcc_mass": (ctypes.c_int, [ctx, dp]),
+        "ddcc_time": (ctypes.c_int64, [ctx]),
+        "ddcc_save": (ctypes.c_int, [ctx, vp, P(ctypes.c_size_t)]),
+        "ddcc_load": (ctypes.c_int, [ctx, vp, ctypes.c_size_t]),
+        "ddcc_sync": (ctypes.c_int, [ctx]),
+        "ddcc_set_tile": (ctypes.c_int, [ctx, ctypes.c_int, ctypes.c_int]),
+        "ddcc_last_error": (ctypes.c_char_p, [ctx]),
+        "ddcc_destroy": (None, [ctx]),
+        "ddcc_version": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+LIB = _load()
+
+# C-named entry points
+ddcc_default_params = LIB.ddcc_default_params
+ddcc_create = LIB.ddcc_create
+ddcc_init_geometry = LIB.ddcc_init_geometry
+ddcc_init_geometry_dev = LIB.ddcc_init_geometry_dev
+ddcc_init_fields = LIB.ddcc_init_fields
+ddcc_init_fields_dev = LIB.ddcc_init_fields_dev
+ddcc_step = LIB.ddcc_step
+ddcc_read_moments = LIB.ddcc_read_moments
+ddcc_read_moments_dev = LIB.ddcc_read_moments_dev
+ddcc_mass = LIB.ddcc_mass
+ddcc_time = LIB.ddcc_time
+ddcc_save = LIB.ddcc_save
+ddcc_load = LIB.ddcc_load
+ddcc_sync = LIB.ddcc_sync
+ddcc_set_tile = LIB.ddcc_set_tile
+ddcc_last_error = LIB.ddcc_last_error
+ddcc_destroy = LIB.ddcc_destroy
+ddcc_version = LIB.ddcc_version
+
+
+def make_params(dim, shape, nphase, lattice_f, lattice_g, precision="fp64",
+                **prm):
+    """Fill a ddcc_params from plain numbers (lattice units). `shape` is the
+    array shape (ny, nx) or (nz, ny, nx); keys as in workloads.default_params:
+    d0, eps, eps0 (penalty lam = 1/eps0^3 unless lam is given), m0, rho0,
+    psi_min, sigma, rho, nu, eta, s_f, s_g (dicts by slot name), accel."""
+    p = ddcc_params()
+    LIB.ddcc_default_params(ctypes.byref(p))
+    p.dim = dim
+    if dim == 2:
+        p.ny, p.nx = shape
+        p.nz = 1
+    else:
+        p.nz, p.ny, p.nx = shape
+    p.nphase = nphase
+    p.lattice_f = LATTICES[lattice_f]
+    p.lattice_g = LATTICES[lattice_g]
+    p.precision = FP64 if precision in ("fp64", FP64) else FP32
+    for key in ("d0", "eps", "m0", "rho0", "psi_min"):
+        if key in prm:
+            setattr(p, key, float(prm[key]))
+    if prm.get("lam") is not None:
+        p.lam = float(prm["lam"])
+    elif prm.get("eps0") is not None:
+        p.lam = 1.0 / float(prm["eps0"]) ** 3
+    if "sigma" in prm:
+        s = np.asarray(prm["sigma"], dtype=np.float64)
+        for i in range(MAX_PHASES):
+            for j in range(MAX_PHASES):
+                p.sigma[i][j] = s[i, j] if (i < nphase and j < nphase) else \
+                    (0.0 if i == j else 1.0)
+    for key in ("rho", "nu", "eta"):
+        if key in prm and prm[key] is not None:
+            v = np.broadcast_to(np.asarray(prm[key], dtype=np.float64),
+                                (nphase,))
+            arr = getattr(p, key)
+            for i in range(nphase):
+                arr[i] = v[i]
+    for key in ("s_f", "s_g"):
+        if key in prm:
+            arr = getattr(p, key)
+            for slot, val in prm[key].items():
+                arr[RATE_SLOTS.index(slot)] = float(val)
+    if "accel" in prm:
+        for a, v in enumerate(prm["accel"]):
+            p.accel[a] = float(v)
+    return p
+
+
+def _dptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _c64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+class Sim:
+    """One library context. Raises DDCCError on any non-zero return code."""
+
+    def __init__(self, params, stream=None):
+        self.params = params
+        self.dim = params.dim
+        self.nphase = params.nphase
+        self.shape = ((params.ny, params.nx) if params.dim == 2 else
+                      (params.nz, params.ny, params.nx))
+        h = ctypes.c_void_p()
+        st = ctypes.c_void_p(stream) if stream is not None else None
+        rc = LIB.ddcc_create(ctypes.byref(params), st, ctypes.byref(h))
+        if rc != DDCC_OK:
+            raise DDCCError(rc, "ddcc_create failed")
+        self._h = h
+
+    @classmethod
+    def from_workload(cls, wl, precision="fp64", stream=None):
+        p = make_params(wl.dim, wl.shape, wl.nphase, wl.lattice_f,
+                        wl.lattice_g, precision, **wl.params)
+        s = cls(p, stream)
+        s.init_geometry(wl.psi, wl.cos_theta_iN)
+        s.init_fields(wl.C0, wl.u0, wl.P0)
+        return s
+
+    def _check(self, rc):
+        if rc != DDCC_OK:
+            raise DDCCError(rc, LIB.ddcc_last_error(self._h).decode())
+
+    def init_geometry(self, psi, cos_theta=None):
+        psi = _c64(psi)
+        ct = None if cos_theta is None else _c64(cos_theta)
+        self._check(LIB.ddcc_init_geometry(self._h, _dptr(psi),
+                                           None if ct is None else _dptr(ct)))
+
+    def init_fields(self, C, u=None, P=None):
+        C = _c64(C)
+        u = None if u is None else _c64(u)
+        P = None if P is None else _c64(P)
+        self._check(LIB.ddcc_init_fields(
+            self._h, _dptr(C), None if u is None else _dptr(u),
+            None if P is None else _dptr(P)))
+
+    def init_geometry_dev(self, psi, cos_theta=None):
+        self._check(LIB.ddcc_init_geometry_dev(
+            self._h, psi.data_ptr(),
+            None if cos_theta is None else cos_theta.data_ptr()))
+
+    def init_fields_dev(self, C, u=None, P=None):
+        self._check(LIB.ddcc_init_fields_dev(
+            self._h, C.data_ptr(), None if u is None else u.data_ptr(),
+            None if P is None else P.data_ptr()))
+
+    def step(self, n=1):
+        self._check(LIB.ddcc_step(self._h, int(n)))
+
+    def read_moments(self):
+        C = np.empty((self.nphase,) + self.shape)
+        u = np.empty((self.dim,) + self.shape)
+        P = np.empty(self.shape)
+        self._check(LIB.ddcc_read_moments(self._h, _dptr(C), _dptr(u),
+                                          _dptr(P)))
+        return C, u, P
+
+    def read_moments_dev(self, C, u, P):
+        self._check(LIB.ddcc_read_moments_dev(self._h, C.data_ptr(),
+                                              u.data_ptr(), P.data_ptr()))
+
+    def mass(self):
+        m = np.empty(self.nphase)
+        self._check(LIB.ddcc_mass(self._h, _dptr(m)))
+        return m
+
+    @property
+    def time(self):
+        return int(LIB.ddcc_time(self._h))
+
+    def save(self):
+        nb = ctypes.c_size_t(0)
+        self._check(LIB.ddcc_save(self._h, None, ctypes.byref(nb)))
+        buf = np.empty(nb.value, dtype=np.uint8)
+        self._check(LIB.ddcc_save(self._h, buf.ctypes.data_as(ctypes.c_void_p),
+                                  ctypes.byref(nb)))
+        return buf
+
+    def load(self, buf):
+        buf = np.ascontiguousarray(buf, dtype=np.uint8)
+        self._check(LIB.ddcc_load(self._h, buf.ctypes.data_as(ctypes.c_void_p),
+                                  buf.nbytes))
+
+    def sync(self):
+        self._check(LIB.ddcc_sync(self._h))
+
+    def set_tile(self, tx=0, ty=0):
+        self._check(LIB.ddcc_set_tile(self._h, int(tx), int(ty)))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            LIB.ddcc_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def unpack_state(sim, buf):
+    """Split a ddcc_save checkpoint into arrays (host side, for tests):
+    f (N, Qf, *shape), g (Qg, *shape) with g_0 stored as g_0 - rho0,
+    hist (nhist, *shape), T (nT, *shape), and the time step."""
+    hdr = np.frombuffer(buf[:8 + 8 * 4 + 16], dtype=np.uint8)
+    head = np.frombuffer(bytes(hdr[8:8 + 32]), dtype=np.int32)
+    dim, nx, ny, nz, N, lf, lg, prec = [int(v) for v in head]
+    t = int(np.frombuffer(bytes(hdr[40:48]), dtype=np.int64)[0])
+    qs = {0: 9, 1: 7, 2: 15, 3: 19}
+    Qf, Qg = qs[lf], qs[lg]
+    shape = (ny, nx) if dim == 2 else (nz, ny, nx)
+    n = nx * ny * nz
+    dt = np.float64 if prec == FP64 else np.float32
+    data = np.frombuffer(bytes(buf[56:]), dtype=dt)
+    nhist = N * dim + dim * (dim + 1) // 2 + 1
+    nT = dim * (dim - 1) // 2
+    o = 0
+    f = data[o:o + N * Qf * n].reshape((N, Qf) + shape)
+    o += N * Qf * n
+    g = data[o:o + Qg * n].reshape((Qg,) + shape)
+    o += Qg * n
+    hist = data[o:o + nhist * n].reshape((nhist,) + shape)
+    o += nhist * n
+    T = data[o:o + nT * n].reshape((nT,) + shape)
+    return dict(f=f, g=g, hist=hist, T=T, t=t, dim=dim, N=N, lf=lf, lg=lg)
+
+
+VELOCITIES = {
+    0: [(0, 0), (1, 0), (0, 1), (-1, 0), (0, -1), (1, 1), (-1, 1), (-1, -1),
+        (1, -1)],
+    2: [(0, 0, 0), (1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1),
+        (0, 0, -1), (1, 1, 1), (1, 1, -1), (1, -1, 1), (1, -1, -1),
+        (-1, 1, 1), (-1, 1, -1), (-1, -1, 1), (-1, -1, -1)],
+    3: [(0, 0, 0), (1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1),
+        (0, 0, -1), (1, 1, 0), (1, -1, 0), (-1, 1, 0), (-1, -1, 0),
+        (1, 0, 1), (1, 0, -1), (-1, 0, 1), (-1, 0, -1), (0, 1, 1),
+        (0, 1, -1), (0, -1, 1), (0, -1, -1)],
+}
+
+
+def streamed(pops, lattice_id):
+    """The checkpoint holds populations before streaming (each step pulls
+    them from x - c_p). Returns the populations after streaming,
+    pops_p(x - c_p), for comparison with a post-streaming state."""
+    out = np.empty_like(pops)
+    for p, c in enumerate(VELOCITIES[lattice_id]):
+        v = pops[..., p, :, :] if pops.ndim == len(c) + 2 else pops[p]
+        r = v
+        for a, ca in enumerate(c):
+            if ca:
+                r = np.roll(r, ca, axis=-1 - a)
+        if pops.ndim == len(c) + 2:
+            out[..., p, :, :] = r
+        else:
+            out[p] = r
+    return out

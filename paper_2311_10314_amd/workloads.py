@@ -1,0 +1,236 @@
+"""Seeded synthetic workloads: geometry (psi), wetting angles and initial
+phase fields for the DD-CCLB step.
+
+This module only draws and shapes inputs; it holds none of the scheme's
+arithmetic. Both the library's tests/bench and the reference checks take
+their inputs from here. Geometry follows the paper's own constructions:
+psi = (1 + tanh(2 d / eps0)) / 2 of the signed distance d (> 0 in the fluid),
+products of such functions for several walls (Section 4.5), droplets with a
+tanh profile of width eps (Section 2.1).
+
+Arrays are (ny, nx) in 2D and (nz, ny, nx) in 3D (x fastest).
+"""
+import math
+
+import numpy as np
+
+PSI_WIDTH = 1.5   # psi = (1 + tanh(d / (sqrt(2) * 1.5))) / 2, i.e. eps0 = 2 sqrt(2) * 1.5
+
+
+class Workload:
+    """Inputs of one run. `params` holds plain numbers in lattice units."""
+
+    def __init__(self, name, dim, shape, lattice_f, lattice_g, params, psi,
+                 cos_theta_iN, C0, u0, P0, steps):
+        self.name = name
+        self.dim = dim
+        self.shape = tuple(shape)
+        self.lattice_f = lattice_f
+        self.lattice_g = lattice_g
+        self.params = params
+        self.psi = psi
+        self.cos_theta_iN = cos_theta_iN
+        self.C0 = C0
+        self.u0 = u0
+        self.P0 = P0
+        self.steps = steps
+
+    @property
+    def nphase(self):
+        return self.C0.shape[0]
+
+    @property
+    def nodes(self):
+        return int(np.prod(self.shape))
+
+
+def _grid(shape):
+    """Coordinate arrays (x, y[, z]) of a grid of the given array shape."""
+    axes = [np.arange(n, dtype=np.float64) for n in shape]
+    mesh = np.meshgrid(*axes, indexing="ij")
+    return tuple(reversed(mesh))   # x, y, (z)
+
+
+def _periodic_delta(a, b, n):
+    d = a - b
+    return d - n * np.round(d / n)
+
+
+def periodic_distance(coords, centre, shape):
+    """Minimum-image Euclidean distance from `centre` (x, y[, z])."""
+    sizes = tuple(reversed(shape))
+    acc = 0.0
+    for xa, ca, n in zip(coords, centre, sizes):
+        acc = acc + _periodic_delta(xa, ca, n) ** 2
+    return np.sqrt(acc)
+
+
+def psi_from_distance(d, width=PSI_WIDTH):
+    """Smooth characteristic function of the fluid region,
+    (1 + tanh(x)) / 2 with x = d / (sqrt(2) width), evaluated as the equal
+    logistic 1 / (1 + exp(-2 x)) so that it does not cancel to exactly 0
+    a few cells inside the solid."""
+    x = np.asarray(d, dtype=np.float64) / (math.sqrt(2.0) * width)
+    return 1.0 / (1.0 + np.exp(np.minimum(-2.0 * x, 700.0)))
+
+
+def droplet(r, radius, eps):
+    """Volume fraction of a droplet: (1 + tanh(2 (R - r) / eps)) / 2."""
+    return 0.5 * (1.0 + np.tanh(2.0 * (radius - r) / eps))
+
+
+def default_params(dim, N, **kw):
+    p = dict(d0=0.4, eps=5.0, eps0=2.0 * math.sqrt(2.0) * PSI_WIDTH, m0=0.05,
+             rho0=1.0, psi_min=1e-30,
+             sigma=[[0.0 if i == j else 0.01 for j in range(N)]
+                    for i in range(N)],
+             rho=[1.0] * N, nu=[0.1] * N,
+             s_f={"0": 1.0, "1": 10.0 / 19.0, "21": 1.2, "22": 1.2, "3": 1.2,
+                  "4": 1.2},
+             s_g={"0": 1.0, "1": 1.2, "3": 1.2, "4": 1.2},
+             accel=[0.0] * dim)
+    p.update(kw)
+    return p
+
+
+def disk_on_droplet_2d(n=128, steps=1000, theta_deg=60.0, r_solid=30.0,
+                       r_drop=20.0):
+    """2D, N = 2: a solid disk at the box centre and a droplet sitting on it
+    (the 128 x 128 case: R_s = 30, droplet R = 20 centred on the disk top)."""
+    shape = (n, n)
+    x, y = _grid(shape)
+    cx = cy = n / 2.0
+    s = n / 128.0
+    rs = r_solid * s
+    rd = r_drop * s
+    d_solid = periodic_distance((x, y), (cx, cy), shape) - rs
+    psi = psi_from_distance(d_solid)
+    r = periodic_distance((x, y), (cx, cy + rs), shape)
+    C1 = droplet(r, rd, 5.0)
+    C0 = np.stack([C1, 1.0 - C1])
+    ct = np.full((1,) + shape, math.cos(math.radians(theta_deg)))
+    return Workload("disk_droplet_2d", 2, shape, "D2Q9", "D2Q9",
+                    default_params(2, 2), psi, ct, C0, np.zeros((2,) + shape),
+                    np.zeros(shape), steps)
+
+
+def porous_bands_2d(n=512, n_disks=40, steps=20000, seed=2311):
+    """2D, N = 3: a periodic porous medium of non-overlapping disks (seeded
+    uniform centres, radii U[10, 30] scaled with n/512), three vertical phase
+    bands, per-obstacle angles theta_13, theta_23 ~ U[45, 135] deg, density
+    ratios 1:10:100 and a body acceleration 1e-6 along x."""
+    rng = np.random.default_rng(seed)
+    shape = (n, n)
+    x, y = _grid(shape)
+    s = n / 512.0
+    eps0 = 2.0 * math.sqrt(2.0) * PSI_WIDTH
+    centres = []
+    radii = []
+    tries = 0
+    while len(centres) < n_disks:
+        tries += 1
+        if tries > 200000:
+            raise RuntimeError("disk packing failed")
+        c = rng.uniform(0.0, n, size=2)
+        r = rng.uniform(10.0, 30.0) * s
+        ok = True
+        for c2, r2 in zip(centres, radii):
+            dx = _periodic_delta(c[0], c2[0], n)
+            dy = _periodic_delta(c[1], c2[1], n)
+            if math.hypot(dx, dy) < r + r2 + 2.0 * eps0:
+                ok = False
+                break
+        if ok:
+            centres.append(c)
+            radii.append(r)
+    theta = rng.uniform(45.0, 135.0, size=(n_disks, 2))
+    psi = np.ones(shape)
+    nearest = np.full(shape, -1, dtype=np.int64)
+    best = np.full(shape, np.inf)
+    for k, (c, r) in enumerate(zip(centres, radii)):
+        dist = periodic_distance((x, y), (c[0], c[1]), shape) - r
+        psi = psi * psi_from_distance(dist)
+        closer = dist < best
+        best = np.where(closer, dist, best)
+        nearest = np.where(closer, k, nearest)
+    ct = np.stack([np.cos(np.radians(theta[nearest, 0])),
+                   np.cos(np.radians(theta[nearest, 1]))])
+    # three vertical bands with tanh edges at x = 0, n/3, 2n/3 (periodic)
+    eps = 5.0
+    edges = [0.0, n / 3.0, 2.0 * n / 3.0]
+    raw = []
+    for b in range(3):
+        lo, hi = edges[b], edges[(b + 1) % 3] if b < 2 else float(n)
+        mid = 0.5 * (lo + hi)
+        half = 0.5 * (hi - lo)
+        dx = np.abs(_periodic_delta(x, mid, n))
+        raw.append(0.5 * (1.0 + np.tanh(2.0 * (half - dx) / eps)))
+    raw = np.stack(raw)
+    C0 = raw / raw.sum(axis=0, keepdims=True)
+    prm = default_params(2, 3, rho=[1.0, 10.0, 100.0],
+                         accel=[1e-6, 0.0])
+    return Workload("porous_bands_2d", 2, shape, "D2Q9", "D2Q9", prm, psi,
+                    ct, C0, np.zeros((2,) + shape), np.zeros(shape), steps)
+
+
+def droplet_impact_sphere_3d(n=256, steps=5000):
+    """3D, N = 2: a solid sphere (R = 60 at (128, 128, 100) for n = 256) and a
+    droplet (R = 40 at (128, 128, 206)) moving towards it at 0.02; density
+    ratio 10, theta = 90 deg; D3Q15 phase sets and a D3Q19 flow set.
+    Sizes scale with n/256."""
+    shape = (n, n, n)
+    x, y, z = _grid(shape)
+    s = n / 256.0
+    sc = (128.0 * s, 128.0 * s, 100.0 * s)
+    dc = (128.0 * s, 128.0 * s, 206.0 * s)
+    d_solid = periodic_distance((x, y, z), sc, shape) - 60.0 * s
+    psi = psi_from_distance(d_solid)
+    r = periodic_distance((x, y, z), dc, shape)
+    eps = 5.0
+    C1 = droplet(r, 40.0 * s, eps)
+    C0 = np.stack([C1, 1.0 - C1])
+    u0 = np.zeros((3,) + shape)
+    u0[2] = -0.02 * C1
+    ct = np.zeros((1,) + shape)    # cos 90 deg
+    prm = default_params(3, 2, rho=[10.0, 1.0])
+    return Workload("droplet_sphere_3d", 3, shape, "D3Q15", "D3Q19", prm,
+                    psi, ct, C0, u0, np.zeros(shape), steps)
+
+
+def random_small(dim, N, shape, seed, lattice_f=None, lattice_g=None,
+                 **params):
+    """Smooth random fields on a small periodic box (used for parity of
+    ragged / odd shapes): a few random solid blobs, random smooth phases
+    normalised to sum 1, random angles, small random velocity."""
+    rng = np.random.default_rng(seed)
+    coords = _grid(shape)
+    psi = np.ones(shape)
+    for _ in range(2):
+        c = [rng.uniform(0, n) for n in reversed(shape)]
+        r = rng.uniform(2.0, 0.25 * min(shape))
+        psi = psi * psi_from_distance(periodic_distance(coords, c, shape) - r)
+    raw = []
+    for _ in range(N):
+        acc = np.full(shape, 0.2)
+        for _ in range(3):
+            c = [rng.uniform(0, n) for n in reversed(shape)]
+            r = rng.uniform(2.0, 0.3 * min(shape))
+            acc = acc + droplet(periodic_distance(coords, c, shape), r, 4.0)
+        raw.append(acc)
+    raw = np.stack(raw)
+    C0 = raw / raw.sum(axis=0, keepdims=True)
+    ct = rng.uniform(-0.7, 0.7, size=(N - 1,) + shape)
+    u0 = rng.uniform(-0.01, 0.01, size=(dim,) + shape)
+    P0 = rng.uniform(-1e-4, 1e-4, size=shape)
+    if lattice_f is None:
+        lattice_f = "D2Q9" if dim == 2 else "D3Q15"
+    if lattice_g is None:
+        lattice_g = "D2Q9" if dim == 2 else "D3Q19"
+    sig = [[0.0 if i == j else 0.01 + 0.002 * (i + j) for j in range(N)]
+           for i in range(N)]
+    prm = default_params(dim, N, sigma=sig,
+                         rho=[1.0 + 2.0 * i for i in range(N)],
+                         nu=[0.1 - 0.02 * i for i in range(N)])
+    prm.update(params)
+    return Workload("random_%dd_n%d" % (dim, N), dim, shape, lattice_f,
+                    lattice_g, prm, psi, ct, C0, u0, P0, 0)

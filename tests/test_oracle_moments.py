@@ -1,0 +1,180 @@
+"""Pins of the oracle's equilibria and sources against the moment identities
+of Appendix B, eq. (B.5b)-(B.5e), and of its pressure constants against the
+recipe of Appendix C (no GPU)."""
+import numpy as np
+import pytest
+
+from oracle import lattices as L
+from oracle import dd_cclb as D
+
+SHAPE = (3, 4)
+
+
+def _moments(lat, pop):
+    m0 = pop.sum(axis=0)
+    m1 = np.array([(lat.c[:, a].reshape((-1,) + (1,) * (pop.ndim - 1))
+                    * pop).sum(0) for a in range(lat.d)])
+    m2 = np.array([[(lat.c[:, a] * lat.c[:, b]).reshape(
+        (-1,) + (1,) * (pop.ndim - 1)) * pop for b in range(lat.d)]
+        for a in range(lat.d)]).sum(axis=2)
+    return m0, m1, m2
+
+
+def _rand(rng, *lead):
+    return rng.normal(size=tuple(lead) + SHAPE)
+
+
+@pytest.mark.parametrize("name,d0", [("D2Q9", 0.4), ("D2Q9", 0.3),
+                                     ("D3Q7", 0.3), ("D3Q15", 0.4),
+                                     ("D3Q19", 0.45)])
+def test_phase_equilibrium_and_source_moments(name, d0):
+    """(B.5b): sum f^eq = phi C, sum c f^eq = phi C u,
+    sum c c f^eq = c_s^2 eta phi mu I;  (B.5c): sum F = 0, sum c F = V."""
+    lat = L.Lattice(name, d0)
+    rng = np.random.default_rng(11)
+    psiC, psimu = _rand(rng), _rand(rng)
+    X = _rand(rng, lat.d)
+    eta = 0.37
+    feq = D.f_equilibrium(lat, psiC, psimu, X, eta)
+    m0, m1, m2 = _moments(lat, feq)
+    assert np.abs(m0 - psiC).max() < 1e-13
+    assert np.abs(m1 - X).max() < 1e-13
+    for a in range(lat.d):
+        for b in range(lat.d):
+            want = lat.cs2 * eta * psimu * (a == b)
+            assert np.abs(m2[a, b] - want).max() < 1e-13
+    V = _rand(rng, lat.d)
+    F = D.f_source(lat, V)
+    m0, m1, _ = _moments(lat, F)
+    assert np.abs(m0).max() < 1e-13
+    assert np.abs(m1 - V).max() < 1e-13
+
+
+@pytest.mark.parametrize("name,d0", [("D2Q9", 0.4), ("D2Q9", 0.3),
+                                     ("D3Q15", 0.4), ("D3Q19", 0.45),
+                                     ("D3Q19", 0.3)])
+def test_flow_equilibrium_and_source_moments(name, d0):
+    """(B.5d): sum g^eq = rho0, sum c g^eq = phi rho u,
+    sum c c g^eq = phi rho u u + sym(phi m^C u) + phi P I;
+    (B.5e): sum G = phi u.grad rho, sum c G = F,
+    sum c c G = c_s^2 phi u.grad rho I + M^{2G}."""
+    lat = L.Lattice(name, d0)
+    d = lat.d
+    rng = np.random.default_rng(12)
+    psiP = _rand(rng)
+    psirho = 1.0 + rng.uniform(size=SHAPE)
+    u = 0.05 * _rand(rng, d)
+    Ysym = _rand(rng, d, d)
+    Y = 0.5 * (Ysym + Ysym.transpose((1, 0) + tuple(range(2, 2 + len(SHAPE)))))
+    geq = D.g_equilibrium(lat, psiP, 1.0, psirho, u, Y)
+    m0, m1, m2 = _moments(lat, geq)
+    assert np.abs(m0 - 1.0).max() < 1e-13
+    assert np.abs(m1 - psirho * u).max() < 1e-13
+    for a in range(d):
+        for b in range(d):
+            want = psirho * u[a] * u[b] + Y[a, b] + psiP * (a == b)
+            assert np.abs(m2[a, b] - want).max() < 1e-12
+    psi = rng.uniform(size=SHAPE)
+    grad_rho = _rand(rng, d)
+    F = _rand(rng, d)
+    M2G = _rand(rng, d, d)
+    M2G = 0.5 * (M2G + M2G.transpose((1, 0) + tuple(range(2, 2 + len(SHAPE)))))
+    G = D.g_source(lat, psi, u, grad_rho, F, M2G)
+    m0, m1, m2 = _moments(lat, G)
+    a0 = psi * (u * grad_rho).sum(0)
+    assert np.abs(m0 - a0).max() < 1e-13
+    assert np.abs(m1 - F).max() < 1e-13
+    for a in range(d):
+        for b in range(d):
+            want = lat.cs2 * a0 * (a == b) + M2G[a, b]
+            assert np.abs(m2[a, b] - want).max() < 1e-12
+
+
+def _pressure_recipe(lat, rates, u, b, dtY, a_grad):
+    """Appendix C: the first-order non-equilibrium rest population is
+    g_0^ne = -dt d_t [(Lambda^-1 g^eq)_0] + dt [(Lambda^-1 G)_0 - G_0 / 2];
+    returns that expression for one node, built from the oracle's own g^eq, G
+    and M^{2G}, with dt = 1 and every other input zero."""
+    S = np.array(lat.rate_vector(rates), float)
+    Linv = lat.Hinv @ np.diag(1.0 / S) @ lat.H
+    d = lat.d
+    one = np.ones(1)
+    z = np.zeros((d, 1))
+    zz = np.zeros((d, d, 1))
+    uu = u.reshape(d, 1)
+    bb = b.reshape(d, 1)
+    M2G = D.m2g_tensor(lat, dtY.reshape(d, d, 1), uu, bb)
+    G = D.g_source(lat, one, uu, a_grad.reshape(d, 1), z, M2G)[:, 0]
+    # d_t g^eq from the d_t Y part only (u-independent terms are constant)
+    dgeq = (D.g_equilibrium(lat, 0 * one, 0.0, one, z, dtY.reshape(d, d, 1))
+            - D.g_equilibrium(lat, 0 * one, 0.0, one, z, zz))[:, 0]
+    return -(Linv @ dgeq)[0] + (Linv @ G)[0] - G[0] / 2.0
+
+
+@pytest.mark.parametrize("name,dim", [("D2Q9", 2), ("D3Q15", 3),
+                                      ("D3Q19", 3)])
+@pytest.mark.parametrize("d0", (0.3, 0.4, 0.45))
+def test_pressure_constants_follow_appendix_c(name, dim, d0):
+    """The constants of eq. (19) are what Appendix C's recipe gives with the
+    oracle's G and M^{2G}: coefficient K(1-d0)(2-s0)/(2 s0) of phi u.grad rho,
+    K/(2 c^2) of d_t(phi m^C.u) and H/s21 of u.grad(phi rho), with the
+    printed K and H (2D: K = 1 - d0, H = K(1-2d0)(s21-2); 3D, D3Q15:
+    K = 1 - 2 d0, H = K(3-7d0)(s21-2)/2). In 3D the recipe matches when the
+    fourth-order rows relax at s21, the approximation behind the printed
+    3D constants; D3Q19 then gives K = w0/(1-d0) with the same H formula."""
+    lat = L.Lattice(name, d0)
+    s21, s0 = 1.37, 1.15
+    rates = {"0": s0, "1": 1.2, "21": s21, "22": 1.5, "3": 1.1,
+             "4": s21 if dim == 3 else 1.3}
+    prm = D.Params(dim=dim, lattice_f=name, lattice_g=name, d0=d0, eps=5.0,
+                   m0=0.05, sigma=[[0, .01], [.01, 0]], rho=[1, 1],
+                   nu=[.1, .1], eps0=4.0)
+    if name == "D2Q9":
+        assert abs(prm.K - (1.0 - d0)) < 1e-15
+    if name == "D3Q15":
+        assert abs(prm.K - (1.0 - 2.0 * d0)) < 1e-15
+    rng = np.random.default_rng(21)
+    u = rng.normal(size=dim)
+    b = rng.normal(size=dim)
+    zero = np.zeros(dim)
+    zz = np.zeros((dim, dim))
+    # u.grad(phi rho) coefficient -> H / s21
+    got = _pressure_recipe(lat, rates, u, b, zz, zero) / (u @ b)
+    assert abs(got - prm.K * prm.Hfac * (s21 - 2.0) / s21) < 1e-12
+    # phi u.grad rho coefficient (source zeroth moment) -> K(1-d0)(2-s0)/(2s0)
+    a_grad = rng.normal(size=dim)
+    got = _pressure_recipe(lat, rates, u, zero, zz, a_grad) / (u @ a_grad)
+    assert abs(got - prm.K * (1.0 - d0) * (2.0 - s0) / (2.0 * s0)) < 1e-12
+    # d_t of the symmetric flux tensor -> K/2 times its trace
+    A = rng.normal(size=(dim, dim))
+    dtY = 0.5 * (A + A.T)
+    got = _pressure_recipe(lat, rates, zero, zero, dtY, zero) / np.trace(dtY)
+    assert abs(got - prm.K / 2.0) < 1e-12
+
+
+def test_component_wise_m2g_does_not_reproduce_eq19():
+    """With M^{2G}'s last term read per component, u_a d_a(phi rho) delta_ab,
+    the same recipe misses the printed 2D H at d0 != 1/3; the printed
+    scalar form is the one consistent with eq. (19)."""
+    lat = L.Lattice("D2Q9", 0.4)
+    rates = {"0": 1.0, "1": 1.2, "21": 1.37, "22": 1.5, "3": 1.1, "4": 1.3}
+    orig = D.m2g_tensor
+
+    def per_component(lat_, dtY, u, gpr):
+        M = orig(lat_, dtY, u, gpr)
+        udotb = sum(u[a] * gpr[a] for a in range(lat_.d))
+        for a in range(lat_.d):
+            M[a, a] += (1.0 - 3.0 * lat_.cs2) * (u[a] * gpr[a] - udotb)
+        return M
+
+    u = np.array([0.3, -0.7])
+    b = np.array([0.5, 0.2])
+    try:
+        D.m2g_tensor = per_component
+        got = _pressure_recipe(lat, rates, u, b, np.zeros((2, 2)),
+                               np.zeros(2)) / (u @ b)
+    finally:
+        D.m2g_tensor = orig
+    K = 0.6
+    printed = K * (1 - 0.8) * (1.37 - 2.0) / 1.37
+    assert abs(got - printed) > 1e-3
