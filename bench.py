@@ -1,0 +1,220 @@
+"""Throughput of the fused DD-CCLB step on one MI355X.
+
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 512] [--skip-cpu]
+
+Workload: the 2D porous medium of the paper's setting (512 x 512 periodic
+box, 40 seeded disks with radii U[10, 30], three vertical phase bands,
+per-obstacle contact angles U[45, 135] deg, densities 1:10:100, body
+acceleration 1e-6), N = 3 phase sets + 1 flow set on D2Q9. One "step" is one
+time step of the whole scheme (one fused kernel launch). Both FP32 and FP64
+are timed; the JSON `value` is the FP32 figure and `fp64` holds the other.
+
+MLUPS counts lattice-node updates per second, each update covering all N + 1
+distribution sets. `roofline.achieved` is the algorithmic HBM bytes of one
+node update (populations read + written once, history read + written once,
+static fields read once) times the nodes of one launch, divided by the
+average launch duration measured with HIP events on the library's stream.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("MLUPS (all distribution sets) and % of HBM roofline, "
+          "FP32 vs FP64 at stated error")
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+KERNEL_SOURCES = ["paper_2311_10314_amd/csrc/step2d.hip",
+                  "paper_2311_10314_amd/csrc/lattice.hpp",
+                  "paper_2311_10314_amd/csrc/coef.hpp"]
+
+
+def algorithmic_bytes_per_node(N, dim, Qf, Qg, esz):
+    """Populations (N Qf + Qg) read and written once, history
+    (N d + d(d+1)/2 + 1 in place, d(d-1)/2 double-buffered) read and written
+    once, psi and N-1 wetting cosines read once."""
+    pops = (N * Qf + Qg) * 2
+    hist = (N * dim + dim * (dim + 1) // 2 + 1) * 2
+    tens = (dim * (dim - 1) // 2) * 2
+    static = 1 + (N - 1)
+    return (pops + hist + tens + static) * esz
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(precision):
+    """HBM bytes per launch from the committed rocprofv3 counter runs, if
+    they were taken on the current kernel source; else None."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    e = t.get(precision)
+    if not e or e.get("kernel_hash") != kernel_source_hash():
+        return None
+    return e.get("bytes_per_launch")
+
+
+def make_workload(n):
+    from paper_2311_10314_amd import workloads as W
+    return W.porous_bands_2d(n=n)
+
+
+def time_gpu(wl, precision, steps, warmup, torch):
+    from paper_2311_10314_amd.ddcc import Sim
+    stream = torch.cuda.Stream()
+    sim = Sim.from_workload(wl, precision, stream=stream.cuda_stream)
+    m0 = sim.mass()
+    sim.step(warmup)
+    sim.sync()
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record(stream)
+    sim.step(steps)
+    t1.record(stream)
+    t1.synchronize()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1)
+    try:
+        m1 = sim.mass()
+        drift = float(max(abs(a - b) / abs(b) for a, b in zip(m1, m0)))
+    except Exception as e:  # a non-finite state is reported, not hidden
+        print("mass check failed: %s" % e, file=sys.stderr, flush=True)
+        drift = None
+    return sim, ms / steps, drift
+
+
+def error_vs_oracle(wl, steps):
+    """Relative L-inf of C_i and u after `steps` steps, GPU vs oracle."""
+    import numpy as np
+
+    import oracle
+    from paper_2311_10314_amd.ddcc import Sim
+    prm, geo, st = oracle.from_workload(wl)
+    st = oracle.run(prm, geo, st, steps)
+    Co, uo, _ = oracle.moments(prm, geo, st)
+    out = {}
+    for prec in ("fp64", "fp32"):
+        sim = Sim.from_workload(wl, prec)
+        sim.step(steps)
+        C, u, _ = sim.read_moments()
+        eC = max(float(np.abs(C[i] - Co[i]).max() / np.abs(Co[i]).max())
+                 for i in range(len(Co)))
+        eu = float(np.abs(u - uo).max() / np.abs(uo).max())
+        out[prec] = {"rel_linf_C": eC, "rel_linf_u": eu, "steps": steps}
+        sim.close()
+    return out
+
+
+def cpu_baseline(wl, steps):
+    """The FP64 oracle, untuned, on a bounded sample of the same workload:
+    `steps` time steps of the full 512 x 512 box, one thread."""
+    import warnings
+
+    from threadpoolctl import threadpool_limits
+
+    import oracle
+    warnings.simplefilter("ignore")
+    with threadpool_limits(limits=1):
+        prm, geo, st = oracle.from_workload(wl)
+        t = time.perf_counter()
+        oracle.run(prm, geo, st, steps)
+        dt = time.perf_counter() - t
+    return {"value": wl.nodes * steps / dt / 1e6, "unit": "MLUPS",
+            "cores": 1, "kind": "oracle",
+            "sample": "%d steps of the full %dx%d N=%d box, numpy float64, "
+                      "1 thread, %.1f s" % (steps, wl.shape[1], wl.shape[0],
+                                             wl.nphase, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--n", type=int, default=512)
+    ap.add_argument("--cpu-steps", type=int, default=8)
+    ap.add_argument("--skip-cpu", action="store_true")
+    ap.add_argument("--tile", type=int, default=0)
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU "
+              "path (see the design notes for how the grid would shard)",
+              file=sys.stderr)
+        return 2
+    import torch
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        return 1
+    wl = make_workload(a.n)
+    N = wl.nphase
+    res = {}
+    for prec, esz in (("fp32", 4), ("fp64", 8)):
+        print("timing %s: %d warmup + %d steps on %s" % (prec, a.warmup,
+                                                         a.steps, wl.shape),
+              file=sys.stderr, flush=True)
+        sim, ms, drift = time_gpu(wl, prec, a.steps, a.warmup, torch)
+        sim.close()
+        bpn = algorithmic_bytes_per_node(N, 2, 9, 9, esz)
+        per_launch = bpn * wl.nodes
+        achieved = per_launch / (ms * 1e-3) / 1e9
+        traffic = measured_traffic(prec)
+        res[prec] = {
+            "value": wl.nodes / (ms * 1e-3) / 1e6,
+            "set_mlups": (N + 1) * wl.nodes / (ms * 1e-3) / 1e6,
+            "ms_per_step": ms,
+            "mass_drift": drift,
+            "roofline": {"bound": "hbm", "achieved": achieved,
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": achieved / HBM_PEAK_GBS,
+                         "traffic": traffic,
+                         "algorithmic_bytes_per_launch": per_launch,
+                         "bytes_per_node": bpn},
+        }
+        print("  %s: %.4f ms/step, %.0f MLUPS, %.0f GB/s" % (
+            prec, ms, res[prec]["value"], achieved), file=sys.stderr,
+            flush=True)
+    err = None
+    cpu = None
+    if not a.skip_cpu:
+        print("error vs oracle (10 steps) and cpu baseline", file=sys.stderr,
+              flush=True)
+        err = error_vs_oracle(wl, 10)
+        cpu = cpu_baseline(wl, a.cpu_steps)
+    f32 = res["fp32"]
+    line = {
+        "metric": METRIC, "value": f32["value"], "unit": "MLUPS",
+        "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": f32["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "porous_bands_2d: %dx%d periodic, N=3 "
+                               "(+1 flow set), D2Q9, 40 disks, rho 1:10:100"
+                               % (a.n, a.n),
+                   "nodes": wl.nodes, "phases": N, "precision": "fp32"},
+        "set_mlups": f32["set_mlups"],
+        "mass_drift": f32["mass_drift"],
+        "roofline": f32["roofline"],
+        "cpu_baseline": cpu,
+        "error_vs_oracle": err,
+        "fp64": res["fp64"],
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

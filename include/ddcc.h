@@ -92,7 +92,8 @@ typedef struct ddcc_params {
                                    from m0 and s_f[1] by eq. (17)            */
   double s_f[6];    /* rates of the phase sets, each in (0, 2)               */
   double s_g[6];    /* rates of the flow set (slots 2, 3 unused)             */
-  double accel[3];  /* body acceleration; adds psi rho a to the force        */
+  double accel[3];  /* body acceleration a; adds psi rho a to the force      */
+  double force[3];  /* body force density G; adds psi G to the force        */
 } ddcc_params;
 
 typedef struct ddcc_ctx ddcc_ctx;

@@ -45,13 +45,15 @@ class Params:
     m0: mobility of eq. (2.5); eta_i derived from eq. (17) unless given.
     eps: fluid-fluid interface width; eps0: diffuse-domain layer thickness.
     lam: penalty coefficient of (1 - psi) u (eq. 2.13c); default 1/eps0^3.
+    accel, force: body acceleration a and body force density G (force psi
+      rho a + psi G).
     s_f: relaxation rates of the phase sets; s_g: those of the flow set
       ('21' and '22' of the flow set always come from nu(x) by eq. (16)).
     """
 
     def __init__(self, *, dim, lattice_f, lattice_g, d0, eps, m0, sigma, rho,
                  nu, eps0=None, lam=None, rho0=1.0, psi_min=1e-30, s_f=None,
-                 s_g=None, eta=None, accel=None):
+                 s_g=None, eta=None, accel=None, force=None):
         self.dim = int(dim)
         self.sigma = np.array(sigma, dtype=np.float64)
         self.N = self.sigma.shape[0]
@@ -87,6 +89,8 @@ class Params:
                                    (self.N,)).copy()
         self.accel = np.zeros(self.dim) if accel is None else \
             np.array(accel, dtype=np.float64)
+        self.force = np.zeros(self.dim) if force is None else \
+            np.array(force, dtype=np.float64)
         # eq. (19) constants. K = w0 / (1 - d0) equals the printed K for both
         # the 2D (1 - d0) and the 3D (1 - 2 d0) lattices; the printed H
         # factor is (1 - 2 d0) in 2D and (3 - 7 d0)/2 in 3D (H also carries
@@ -445,14 +449,15 @@ def macroscopic(prm, geo, st):
                   for a in range(d)])
     sum_g_moving = st.g[1:].sum(axis=0)
     # eq. (3.13): F = -div T + sum_i phi mu_i grad C_i + P grad phi
-    #               - (1 - phi) lam u (+ phi rho a for a body acceleration).
+    #               - (1 - phi) lam u, plus phi (rho a + G) for a body
+    #               acceleration a or a body force density G.
     # Reading: T and P are taken from the previous step (they need u);
     # the penalty is solved implicitly with the velocity recovery below.
     Fp = -div_tensor(st.T, d) + st.P * geo.grad_psi
     for i in range(N):
         Fp += q["psimu"][i] * q["gradC"][i]
     for a in range(d):
-        Fp[a] += psirho * prm.accel[a]
+        Fp[a] += psirho * prm.accel[a] + psi * prm.force[a]
     # phi rho u = sum_p c_p g_p + F/2 with F = Fp - (1 - phi) lam u
     u = (j + 0.5 * Fp) / (psirho + 0.5 * (1.0 - psi) * prm.lam)
     F = Fp - (1.0 - psi) * prm.lam * u

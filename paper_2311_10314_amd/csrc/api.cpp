@@ -201,8 +201,8 @@ int validate(const ddcc_params* p, std::string& msg) {
     }
   }
   for (int a = 0; a < 3; ++a)
-    if (!finite(p->accel[a])) {
-      msg = "non-finite body acceleration";
+    if (!finite(p->accel[a]) || !finite(p->force[a])) {
+      msg = "non-finite body acceleration or force";
       return DDCC_E_INVAL;
     }
   return DDCC_OK;
@@ -259,7 +259,10 @@ void fill_coef(const ddcc_params& p, long long n, Coef<R>& k) {
   k.halfK = R(0.5 * K);
   k.KH = R(p.dim == 2 ? K * (1.0 - 2.0 * p.d0) : K * (3.0 - 7.0 * p.d0) / 2.0);
   k.one_m3cs2 = R(1.0 - 3.0 * cs2);
-  for (int a = 0; a < 3; ++a) k.accel[a] = R(p.accel[a]);
+  for (int a = 0; a < 3; ++a) {
+    k.accel[a] = R(p.accel[a]);
+    k.force[a] = R(p.force[a]);
+  }
 }
 
 template <class S>

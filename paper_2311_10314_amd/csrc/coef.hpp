@@ -32,7 +32,8 @@ struct Coef {
   R halfK;                // K / (2 c^2)                (eq. 19)
   R KH;                   // K * (1 - 2 d0) in 2D, K (3 - 7 d0)/2 in 3D
   R one_m3cs2;            // c^2 - 3 c_s^2              (eq. 3.12)
-  R accel[3];
+  R accel[3];             // body acceleration: force psi rho a
+  R force[3];             // body force density: force psi G
 };
 
 }  // namespace ddcc

@@ -349,12 +349,14 @@ struct Step2D {
         if (D2Q9::c[p].y) j[1] += R(D2Q9::c[p].y) * gp[p];
       }
       // force (eq. 3.13): -div T^{n-1} + sum_i phi mu_i grad C_i
-      //                   + P^{n-1} grad psi + psi rho a
+      //                   + P^{n-1} grad psi + psi (rho a + G)
       const Patch<R> tp = patch(sm.T, mx, my);
       const R Pprev = ld<S, R>(b.hist + (2 * N + 3) * n + idx);
       R Fp[2];
-      Fp[0] = grad_y(tp) + Pprev * gpsi[0] + psirho * k.accel[0];
-      Fp[1] = -grad_x(tp) + Pprev * gpsi[1] + psirho * k.accel[1];
+      Fp[0] = grad_y(tp) + Pprev * gpsi[0] + psirho * k.accel[0] +
+              psi * k.force[0];
+      Fp[1] = -grad_x(tp) + Pprev * gpsi[1] + psirho * k.accel[1] +
+              psi * k.force[1];
 #pragma unroll
       for (int i = 0; i < N; ++i) {
         Fp[0] += psimu[i] * gC[i][0];

@@ -45,6 +45,7 @@ class ddcc_params(ctypes.Structure):
         ("eta", ctypes.c_double * MAX_PHASES),
         ("s_f", ctypes.c_double * 6), ("s_g", ctypes.c_double * 6),
         ("accel", ctypes.c_double * 3),
+        ("force", ctypes.c_double * 3),
     ]
 
 
@@ -119,7 +120,8 @@ def make_params(dim, shape, nphase, lattice_f, lattice_g, precision="fp64",
     """Fill a ddcc_params from plain numbers (lattice units). `shape` is the
     array shape (ny, nx) or (nz, ny, nx); keys as in workloads.default_params:
     d0, eps, eps0 (penalty lam = 1/eps0^3 unless lam is given), m0, rho0,
-    psi_min, sigma, rho, nu, eta, s_f, s_g (dicts by slot name), accel."""
+    psi_min, sigma, rho, nu, eta, s_f, s_g (dicts by slot name), accel,
+    force."""
     p = ddcc_params()
     LIB.ddcc_default_params(ctypes.byref(p))
     p.dim = dim
@@ -157,9 +159,11 @@ def make_params(dim, shape, nphase, lattice_f, lattice_g, precision="fp64",
             arr = getattr(p, key)
             for slot, val in prm[key].items():
                 arr[RATE_SLOTS.index(slot)] = float(val)
-    if "accel" in prm:
-        for a, v in enumerate(prm["accel"]):
-            p.accel[a] = float(v)
+    for key in ("accel", "force"):
+        if key in prm and prm[key] is not None:
+            arr = getattr(p, key)
+            for a, v in enumerate(prm[key]):
+                arr[a] = float(v)
     return p
 
 

@@ -28,3 +28,33 @@ def small_cases():
         W.random_small(2, 4, (11, 130), seed=3),
         W.random_small(2, 2, (9, 13), seed=4),
     ]
+
+
+def gpu_state_to_oracle(wl, sim):
+    """Oracle State built from a library checkpoint (populations after
+    streaming, g_0 with rho0 added back, history unpacked)."""
+    from oracle.dd_cclb import State
+    from paper_2311_10314_amd.ddcc import streamed, unpack_state
+    s = unpack_state(sim, sim.save())
+    N, d = s["N"], s["dim"]
+    f = np.stack([streamed(np.asarray(s["f"][i], np.float64), s["lf"])
+                  for i in range(N)])
+    g = streamed(np.asarray(s["g"], np.float64), s["lg"])
+    g[0] += wl.params["rho0"]
+    h = np.asarray(s["hist"], np.float64)
+    shape = wl.shape
+    X = h[:N * d].reshape((N, d) + shape)
+    Y = np.zeros((d, d) + shape)
+    T = np.zeros((d, d) + shape)
+    o = N * d
+    pairs = [(a, b) for a in range(d) for b in range(a, d)]
+    for k, (a, b) in enumerate(pairs):
+        Y[a, b] = h[o + k]
+        Y[b, a] = h[o + k]
+    P = h[o + len(pairs)].copy()
+    tpairs = [(a, b) for a in range(d) for b in range(a + 1, d)]
+    Tg = np.asarray(s["T"], np.float64)
+    for k, (a, b) in enumerate(tpairs):
+        T[a, b] = Tg[k]
+        T[b, a] = -Tg[k]
+    return State(f, g, X, Y, P, T)

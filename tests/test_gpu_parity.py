@@ -7,7 +7,8 @@ import numpy as np
 import pytest
 
 from paper_2311_10314_amd import workloads as W
-from tests.helpers import oracle_run, rel_linf, small_cases
+from tests.helpers import (gpu_state_to_oracle, oracle_run, rel_linf,
+                           small_cases)
 
 pytestmark = pytest.mark.gpu
 
@@ -111,3 +112,57 @@ def test_short_run_fp32(k):
     assert e["C"] < 1e-5 and e["u"] < 1e-4
     drift = np.abs(g["mass"] - g["mass0"]) / np.abs(g["mass0"])
     assert drift.max() < 1e-6
+
+
+def test_disk_droplet_1000_steps_fp32():
+    """Same case in FP32 storage and arithmetic: C_i and u within 1e-5 of the
+    FP64 oracle after 1000 steps, mass drift below 1e-6."""
+    wl = W.disk_on_droplet_2d(n=128)
+    o = oracle_run(wl, 1000)
+    g = gpu_run(wl, 1000, "fp32")
+    e = _report("disk 1000 fp32", g, o)
+    assert e["C"] < 1e-5 and e["u"] < 1e-5
+    drift = np.abs(g["mass"] - g["mass0"]) / np.abs(g["mass0"])
+    print("fp32 drift", drift, flush=True)
+    assert drift.max() < 1e-6
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 2e-5)])
+def test_porous_full_size_one_step(precision, tol):
+    """Full 512 x 512 N = 3 porous workload in the bench's launch shape: the
+    GPU state after 300 steps, advanced one step by the oracle, matches the
+    GPU's own next step at every node (C_i, u, P, populations)."""
+    import oracle
+    wl = W.porous_bands_2d(n=512)
+    from paper_2311_10314_amd.ddcc import Sim
+    sim = Sim.from_workload(wl, precision)
+    sim.step(300)
+    st = gpu_state_to_oracle(wl, sim)
+    prm, geo, _ = oracle.from_workload(wl)
+    st1 = oracle.step(prm, geo, st)
+    Co, uo, Po = oracle.moments(prm, geo, st1)
+    sim.step(1)
+    C, u, P = sim.read_moments()
+    eC = max(rel_linf(C[i], Co[i]) for i in range(3))
+    eu = rel_linf(u, uo)
+    fl = wl.psi >= 1e-3
+    eP = rel_linf(P[fl], Po[fl])
+    g1 = gpu_state_to_oracle(wl, sim)
+    ef = np.abs(g1.f - st1.f).max() / np.abs(st1.f).max()
+    eg = np.abs(g1.g - st1.g).max() / np.abs(st1.g).max()
+    print("%s one step at 300: C %.2e u %.2e P %.2e f %.2e g %.2e" % (
+        precision, eC, eu, eP, ef, eg), flush=True)
+    # P is recovered through eq. (19) from sums of small populations, so it
+    # carries ~100x the relative round-off of the populations themselves.
+    assert max(eC, eu, ef, eg) < tol and eP < 100 * tol
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 1e-4)])
+def test_porous_reduced_100_steps(precision, tol):
+    """256 x 256 version of the porous workload (same generator, radii scaled
+    by 1/2), 100 steps against the oracle."""
+    wl = W.porous_bands_2d(n=256)
+    o = oracle_run(wl, 100)
+    g = gpu_run(wl, 100, precision)
+    e = _report("porous256 %s" % precision, g, o)
+    assert e["C"] < tol and e["u"] < tol
