@@ -34,14 +34,15 @@ KERNEL_SOURCES = ["paper_2311_10314_amd/csrc/step2d.hip",
 
 
 def algorithmic_bytes_per_node(N, dim, Qf, Qg, esz):
-    """Populations (N Qf + Qg) read and written once, history
+    """Populations (N Qf + Qg) read and written once (the N rest populations
+    of the phase sets are float64 in both precisions), history
     (N d + d(d+1)/2 + 1 in place, d(d-1)/2 double-buffered) read and written
     once, psi and N-1 wetting cosines read once."""
-    pops = (N * Qf + Qg) * 2
+    pops = (N * (Qf - 1) + Qg) * 2 * esz + N * 2 * 8
     hist = (N * dim + dim * (dim + 1) // 2 + 1) * 2
     tens = (dim * (dim - 1) // 2) * 2
     static = 1 + (N - 1)
-    return (pops + hist + tens + static) * esz
+    return pops + (hist + tens + static) * esz
 
 
 def kernel_source_hash():

@@ -23,6 +23,7 @@ struct ddcc_ctx {
   int Qf = 0, Qg = 0, nhist = 0, nT = 0;
   size_t esz = 8;
   void* f[2] = {nullptr, nullptr};
+  double* f0[2] = {nullptr, nullptr};  // rest populations, float64
   void* g[2] = {nullptr, nullptr};
   void* T[2] = {nullptr, nullptr};
   void* hist = nullptr;
@@ -270,14 +271,17 @@ Bufs<S> bufs(ddcc_ctx* c, int mode) {
   Bufs<S> b{};
   const int a = c->cur, o = c->cur ^ 1;
   b.fA = static_cast<const S*>(c->f[a]);
+  b.f0A = c->f0[a];
   b.gA = static_cast<const S*>(c->g[a]);
   b.TA = static_cast<const S*>(c->T[a]);
   if (mode == MODE_INIT) {
     b.fB = static_cast<S*>(c->f[a]);
+    b.f0B = c->f0[a];
     b.gB = static_cast<S*>(c->g[a]);
     b.TB = static_cast<S*>(c->T[a]);
   } else {
     b.fB = static_cast<S*>(c->f[o]);
+    b.f0B = c->f0[o];
     b.gB = static_cast<S*>(c->g[o]);
     b.TB = static_cast<S*>(c->T[o]);
   }
@@ -298,10 +302,10 @@ hipError_t launch(ddcc_ctx* c, int mode, const double* inC, const double* inU,
     b.outU = oU;
     b.outP = oP;
     if (c->p.dim == 2)
-      return launch_2d<double, double>(c->p.nphase, mode, c->kd, b, c->tile_y,
-                                       c->stream);
-    return launch_3d<double, double>(c->p.nphase, mode, c->kd, b, c->tile_x,
-                                     c->tile_y, c->stream);
+      return launch_2d<double, double>(c->p.nphase, mode, c->kd, c->kd, b,
+                                       c->tile_y, c->stream);
+    return launch_3d<double, double>(c->p.nphase, mode, c->kd, c->kd, b,
+                                     c->tile_x, c->tile_y, c->stream);
   }
   Bufs<float> b = bufs<float>(c, mode);
   b.inC = inC;
@@ -311,10 +315,10 @@ hipError_t launch(ddcc_ctx* c, int mode, const double* inC, const double* inU,
   b.outU = oU;
   b.outP = oP;
   if (c->p.dim == 2)
-    return launch_2d<float, float>(c->p.nphase, mode, c->kf, b, c->tile_y,
-                                   c->stream);
-  return launch_3d<float, float>(c->p.nphase, mode, c->kf, b, c->tile_x,
-                                 c->tile_y, c->stream);
+    return launch_2d<float, float>(c->p.nphase, mode, c->kd, c->kf, b,
+                                   c->tile_y, c->stream);
+  return launch_3d<float, float>(c->p.nphase, mode, c->kd, c->kf, b,
+                                 c->tile_x, c->tile_y, c->stream);
 }
 
 int ensure_staging(ddcc_ctx* c) {
@@ -347,8 +351,9 @@ int upload(ddcc_ctx* c, const double* src, void* dst, size_t count) {
 }
 
 void release(ddcc_ctx* c) {
-  void* ptrs[] = {c->f[0], c->f[1], c->g[0], c->g[1], c->T[0], c->T[1],
-                  c->hist, c->psi,  c->ct,   c->staging, c->partial, c->bad};
+  void* ptrs[] = {c->f[0],  c->f[1],   c->f0[0],    c->f0[1], c->g[0],
+                  c->g[1],  c->T[0],   c->T[1],     c->hist,  c->psi,
+                  c->ct,    c->staging, c->partial, c->bad};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
@@ -421,7 +426,7 @@ int ddcc_create(const ddcc_params* p, void* stream, ddcc_ctx** out) {
   c->nT = d * (d - 1) / 2;
   c->esz = p->precision == DDCC_FP64 ? 8 : 4;
   c->tile_y = d == 2 ? 8 : 4;
-  c->tile_x = d == 2 ? 64 : 32;
+  c->tile_x = 64;
   if (hipGetDevice(&c->device) != hipSuccess) {
     delete c;
     return DDCC_E_HIP;
@@ -444,6 +449,8 @@ int ddcc_create(const ddcc_params* p, void* stream, ddcc_ctx** out) {
   hipError_t e = hipSuccess;
   for (int a = 0; a < 2 && e == hipSuccess; ++a) {
     e = hipMalloc(&c->f[a], sf);
+    if (e == hipSuccess)
+      e = hipMalloc(&c->f0[a], (size_t)p->nphase * n * sizeof(double));
     if (e == hipSuccess) e = hipMalloc(&c->g[a], sg);
     if (e == hipSuccess) e = hipMalloc(&c->T[a], sT);
   }
@@ -466,7 +473,7 @@ int ddcc_create(const ddcc_params* p, void* stream, ddcc_ctx** out) {
     // The 3D kernels are built per (phase, flow) lattice pair; the host
     // checks the pair here so that create fails early when it is absent.
     if (!(p->lattice_f == DDCC_D3Q15 && p->lattice_g == DDCC_D3Q19) ||
-        !have_3d()) {
+        p->nphase > 3 || !have_3d()) {
       release(c);
       delete c;
       return DDCC_E_UNSUPPORTED;
@@ -644,10 +651,12 @@ int ddcc_mass(ddcc_ctx* c, double* mass) {
   const int N = c->p.nphase;
   hipError_t e =
       c->p.precision == DDCC_FP64
-          ? launch_mass<double>(static_cast<const double*>(c->f[c->cur]), N,
+          ? launch_mass<double>(c->f0[c->cur],
+                                static_cast<const double*>(c->f[c->cur]), N,
                                 c->Qf, c->n, c->partial, c->bad,
                                 c->mass_blocks, c->stream)
-          : launch_mass<float>(static_cast<const float*>(c->f[c->cur]), N,
+          : launch_mass<float>(c->f0[c->cur],
+                               static_cast<const float*>(c->f[c->cur]), N,
                                c->Qf, c->n, c->partial, c->bad, c->mass_blocks,
                                c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "mass kernel");
@@ -680,14 +689,15 @@ int ddcc_save(ddcc_ctx* c, void* buf, size_t* bytes) {
   const size_t sg = (size_t)c->Qg * n * c->esz;
   const size_t sh = (size_t)c->nhist * n * c->esz;
   const size_t sT = (size_t)c->nT * n * c->esz;
-  const size_t need = sizeof(SaveHeader) + sf + sg + sh + sT;
+  const size_t s0 = (size_t)c->p.nphase * n * sizeof(double);
+  const size_t need = sizeof(SaveHeader) + sf + s0 + sg + sh + sT;
   if (!buf) {
     *bytes = need;
     return DDCC_OK;
   }
   if (*bytes < need) return fail(c, DDCC_E_INVAL, "buffer too small");
   SaveHeader h{};
-  std::memcpy(h.magic, "DDCCSAV1", 8);
+  std::memcpy(h.magic, "DDCCSAV2", 8);
   h.dim = c->p.dim;
   h.nx = c->p.nx;
   h.ny = c->p.ny;
@@ -704,6 +714,10 @@ int ddcc_save(ddcc_ctx* c, void* buf, size_t* bytes) {
   HIPCHK(c, hipMemcpyAsync(o, c->f[c->cur], sf, hipMemcpyDeviceToHost, c->stream),
          "save f");
   o += sf;
+  HIPCHK(c, hipMemcpyAsync(o, c->f0[c->cur], s0, hipMemcpyDeviceToHost,
+                           c->stream),
+         "save f0");
+  o += s0;
   HIPCHK(c, hipMemcpyAsync(o, c->g[c->cur], sg, hipMemcpyDeviceToHost, c->stream),
          "save g");
   o += sg;
@@ -727,11 +741,12 @@ int ddcc_load(ddcc_ctx* c, const void* buf, size_t bytes) {
   const size_t sg = (size_t)c->Qg * n * c->esz;
   const size_t sh = (size_t)c->nhist * n * c->esz;
   const size_t sT = (size_t)c->nT * n * c->esz;
-  const size_t need = sizeof(SaveHeader) + sf + sg + sh + sT;
+  const size_t s0 = (size_t)c->p.nphase * n * sizeof(double);
+  const size_t need = sizeof(SaveHeader) + sf + s0 + sg + sh + sT;
   if (bytes < need) return fail(c, DDCC_E_INVAL, "checkpoint too small");
   SaveHeader h;
   std::memcpy(&h, buf, sizeof(h));
-  if (std::memcmp(h.magic, "DDCCSAV1", 8) != 0 || h.dim != c->p.dim ||
+  if (std::memcmp(h.magic, "DDCCSAV2", 8) != 0 || h.dim != c->p.dim ||
       h.nx != c->p.nx || h.ny != c->p.ny || h.nz != c->p.nz ||
       h.nphase != c->p.nphase || h.lattice_f != c->p.lattice_f ||
       h.lattice_g != c->p.lattice_g || h.precision != c->p.precision ||
@@ -741,6 +756,10 @@ int ddcc_load(ddcc_ctx* c, const void* buf, size_t bytes) {
   HIPCHK(c, hipMemcpyAsync(c->f[c->cur], s, sf, hipMemcpyHostToDevice, c->stream),
          "load f");
   s += sf;
+  HIPCHK(c, hipMemcpyAsync(c->f0[c->cur], s, s0, hipMemcpyHostToDevice,
+                           c->stream),
+         "load f0");
+  s += s0;
   HIPCHK(c, hipMemcpyAsync(c->g[c->cur], s, sg, hipMemcpyHostToDevice, c->stream),
          "load g");
   s += sg;
@@ -772,10 +791,10 @@ int ddcc_set_tile(ddcc_ctx* c, int tx, int ty) {
       return fail(c, DDCC_E_INVAL, "2D tile height must be 2, 4 or 8");
     if (ty) c->tile_y = ty;
   } else {
-    if (tx != 0 && tx != 32 && tx != 64)
-      return fail(c, DDCC_E_INVAL, "3D tile width must be 32 or 64");
-    if (ty != 0 && ty != 4 && ty != 8)
-      return fail(c, DDCC_E_INVAL, "3D tile height must be 4 or 8");
+    if (tx != 0 && tx != 64)
+      return fail(c, DDCC_E_INVAL, "3D tiles are 64 nodes wide");
+    if (ty != 0 && ty != 2 && ty != 4)
+      return fail(c, DDCC_E_INVAL, "3D tile height must be 2 or 4");
     if (tx) c->tile_x = tx;
     if (ty) c->tile_y = ty;
   }

@@ -15,8 +15,10 @@ enum { MODE_STEP = 0, MODE_INIT = 1, MODE_MOMENTS = 2 };
 //   in MODE_MOMENTS they write outC/outU/outP and nothing else.
 template <class S>
 struct Bufs {
-  const S* fA;
+  const S* fA;     // phase populations [N][Q][n]; plane p = 0 unused
   S* fB;
+  const double* f0A;  // rest populations of the phase sets [N][n], float64
+  double* f0B;
   const S* gA;
   S* gB;
   S* hist;
@@ -32,19 +34,25 @@ struct Bufs {
   double* outP;
 };
 
+// kd: the float64 constants (fields C, mu, psi, rest populations);
+// k: the same constants in the collision arithmetic type R.
 template <class S, class R>
-hipError_t launch_2d(int nphase, int mode, const Coef<R>& k, const Bufs<S>& b,
-                     int ty, hipStream_t st);
+hipError_t launch_2d(int nphase, int mode, const Coef<double>& kd,
+                     const Coef<R>& k, const Bufs<S>& b, int ty,
+                     hipStream_t st);
 
 template <class S, class R>
-hipError_t launch_3d(int nphase, int mode, const Coef<R>& k, const Bufs<S>& b,
-                     int tx, int ty, hipStream_t st);
+hipError_t launch_3d(int nphase, int mode, const Coef<double>& kd,
+                     const Coef<R>& k, const Bufs<S>& b, int tx, int ty,
+                     hipStream_t st);
 
-// Per-phase sums of all populations of `f` (layout [N][Q][n]) into
-// partial[block * N + i], plus a non-finite flag per block in bad[block].
+// Per-phase sums of all populations (rest plane f0 [N][n] plus planes
+// p >= 1 of f [N][Q][n]) into partial[block * N + i], plus a non-finite flag
+// per block in bad[block].
 template <class S>
-hipError_t launch_mass(const S* f, int nphase, int Q, long long n,
-                       double* partial, int* bad, int nblocks, hipStream_t st);
+hipError_t launch_mass(const double* f0, const S* f, int nphase, int Q,
+                       long long n, double* partial, int* bad, int nblocks,
+                       hipStream_t st);
 
 // dst[i] = S(src[i]) for i < count.
 template <class S>

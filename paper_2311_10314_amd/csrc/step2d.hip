@@ -17,14 +17,19 @@
 // The same kernel body also serves initialisation (populations at
 // equilibrium) and moment read-out, selected by a template parameter.
 //
-// Storage S (float/double), arithmetic R (float/double). The rest population
-// of the flow set is stored as g_0 - rho0 (small), every other population
-// raw. History per node: phi C_i u (N x 2), the symmetric flux tensor Y
+// Storage S (float/double), collision arithmetic R (float/double). The
+// volume fractions, chemical potentials and the LDS fields (psi, phi rho, C,
+// mu) are always float64: mu is a small difference of O(beta) terms near
+// equilibrium, and the rest populations of the phase sets (O(1), about
+// phi C_i) are kept in a float64 plane f0 so that phase mass does not drift
+// with float32 rounding. The rest population of the flow set is stored as
+// g_0 - rho0 (small); every other population is raw in S. History per node: phi C_i u (N x 2), the symmetric flux tensor Y
 // (xx, xy, yy) and P, updated in place; the antisymmetric tensor T (xy) is
 // double-buffered because neighbours read it.
 #include <hip/hip_runtime.h>
 
 #include "coef.hpp"
+#include "common.hpp"
 #include "kernels.hpp"
 #include "lattice.hpp"
 
@@ -33,17 +38,6 @@ namespace ddcc {
 namespace {
 
 constexpr int TX = 64;
-
-template <class R>
-__device__ inline R gprime(R C) {
-  // g(C) = C^2 (C - 1)^2  =>  g'(C) = 2 C (C - 1)(2 C - 1)   (Section 2.1)
-  return R(2) * C * (C - R(1)) * (R(2) * C - R(1));
-}
-
-__device__ inline int wrap(int v, int n) {
-  int m = v % n;
-  return m < 0 ? m + n : m;
-}
 
 // Fixed isotropic finite-difference stencil (D2Q9 weights at d0 = 1/3
 // divided by its c_s^2 = 1/3): 1/3 on the axes, 1/12 on the diagonals.
@@ -90,11 +84,6 @@ __device__ inline Patch<R> patch(const R (&a)[H][W], int x, int y) {
   return p;
 }
 
-template <class S, class R>
-__device__ inline R ld(const S* p) {
-  return static_cast<R>(*p);
-}
-
 // Pull: population p at (gx, gy) comes from (gx - c_px, gy - c_py).
 struct Nbr {
   int xm, xp, ym, yp, x, y, nx;
@@ -119,6 +108,7 @@ __device__ inline Nbr make_nbr(int gx, int gy, int nx, int ny) {
 
 template <int N, class S, class R, int MODE, int TY>
 struct Step2D {
+  using D = double;
   static constexpr int Q = 9;
   static constexpr int NT = TX * TY;
   static constexpr int HX = TX + 4, HY = TY + 4;  // C region (halo 2)
@@ -127,10 +117,10 @@ struct Step2D {
   static constexpr int RING2 = MX * MY - TX * TY;
 
   struct Smem {
-    R psi[HY][HX];
-    R prho[HY][HX];
-    R C[N][HY][HX];
-    R mu[N][MY][MX];
+    D psi[HY][HX];
+    D prho[HY][HX];
+    D C[N][HY][HX];
+    D mu[N][MY][MX];
     R T[MY][MX];
   };
 
@@ -165,38 +155,39 @@ struct Step2D {
   }
 
   // Phase 1 at C-region coordinates (lx, ly).
-  __device__ static inline void node1(Smem& sm, const Coef<R>& k,
+  __device__ static inline void node1(Smem& sm, const Coef<D>& k,
                                       const Bufs<S>& b, int x0, int y0, int lx,
-                                      int ly, R* psiC_out) {
+                                      int ly, D* psiC_out) {
     const int gx = wrap(x0 + lx - 2, k.nx), gy = wrap(y0 + ly - 2, k.ny);
     const long long idx = (long long)gy * k.nx + gx;
-    const R psi = ld<S, R>(b.psi + idx);
-    R rho = R(0);
+    const D psi = ld<S, D>(b.psi + idx);
+    D rho = D(0);
     if constexpr (MODE == MODE_INIT) {
 #pragma unroll
-      for (int i = 0; i < N; ++i)
-        psiC_out[i] = psi * R(b.inC[i * k.n + idx]);
+      for (int i = 0; i < N; ++i) psiC_out[i] = psi * b.inC[i * k.n + idx];
     } else {
       const Nbr nb = make_nbr(gx, gy, k.nx, k.ny);
 #pragma unroll
       for (int i = 0; i < N; ++i) {
+        // phi C_i = sum_p f^i_p (Section 3); the rest population does not
+        // move and lives in the float64 plane
         const S* f = b.fA + (long long)i * Q * k.n;
-        R s = R(0);
+        D s = b.f0A[i * k.n + idx];
 #pragma unroll
-        for (int p = 0; p < Q; ++p)
-          s += ld<S, R>(f + p * k.n + nb.src(D2Q9::c[p].x, D2Q9::c[p].y));
+        for (int p = 1; p < Q; ++p)
+          s += ld<S, D>(f + p * k.n + nb.src(D2Q9::c[p].x, D2Q9::c[p].y));
         psiC_out[i] = s;
       }
     }
     // C_i = phi C_i / sum_j phi C_j: equal to phi C_i / phi while the
     // constraint sum_j C_j = 1 of Section 2.1 holds, and keeps it exact.
-    R tot = R(0);
+    D tot = D(0);
 #pragma unroll
     for (int i = 0; i < N; ++i) tot += psiC_out[i];
-    const R inv = R(1) / (tot > k.psi_min ? tot : k.psi_min);
+    const D inv = D(1) / (tot > k.psi_min ? tot : k.psi_min);
 #pragma unroll
     for (int i = 0; i < N; ++i) {
-      const R C = psiC_out[i] * inv;
+      const D C = psiC_out[i] * inv;
       sm.C[i][ly][lx] = C;
       rho += k.rho[i] * C;
     }
@@ -205,45 +196,45 @@ struct Step2D {
   }
 
   // Phase 2 at mu-region coordinates (mx, my): phi mu_i (eq. 2.14).
-  __device__ static inline void node2(Smem& sm, const Coef<R>& k,
+  __device__ static inline void node2(Smem& sm, const Coef<D>& k,
                                       const Bufs<S>& b, int x0, int y0, int mx,
-                                      int my, R* psimu_out) {
+                                      int my, D* psimu_out) {
     const int lx = mx + 1, ly = my + 1;
     const int gx = wrap(x0 + mx - 1, k.nx), gy = wrap(y0 + my - 1, k.ny);
     const long long idx = (long long)gy * k.nx + gx;
-    const Patch<R> ps = patch(sm.psi, lx, ly);
-    const R psi = ps.v[1][1];
-    const R psih = psi > k.psi_min ? psi : k.psi_min;
-    const R gpx = grad_x(ps), gpy = grad_y(ps);
-    const R agp = sqrt(gpx * gpx + gpy * gpy);
-    R C[N], L[N];
+    const Patch<D> ps = patch(sm.psi, lx, ly);
+    const D psi = ps.v[1][1];
+    const D psih = psi > k.psi_min ? psi : k.psi_min;
+    const D gpx = grad_x(ps), gpy = grad_y(ps);
+    const D agp = sqrt(gpx * gpx + gpy * gpy);
+    D C[N], L[N];
 #pragma unroll
     for (int j = 0; j < N; ++j) {
-      const Patch<R> cp = patch(sm.C[j], lx, ly);
+      const Patch<D> cp = patch(sm.C[j], lx, ly);
       C[j] = cp.v[1][1];
       L[j] = div_psi_grad(ps, cp);
     }
     // cos theta_jq from the N-1 stored cos theta_iN (eq. 2.9)
-    R ct[N];
+    D ct[N];
 #pragma unroll
-    for (int i = 0; i < N - 1; ++i) ct[i] = ld<S, R>(b.ct + i * k.n + idx);
-    ct[N - 1] = R(0);
-    R W[N];  // sum_{q != j} cos theta_jq C_j C_q
+    for (int i = 0; i < N - 1; ++i) ct[i] = ld<S, D>(b.ct + i * k.n + idx);
+    ct[N - 1] = D(0);
+    D W[N];  // sum_{q != j} cos theta_jq C_j C_q
 #pragma unroll
     for (int j = 0; j < N; ++j) {
-      R acc = R(0);
+      D acc = D(0);
 #pragma unroll
       for (int q = 0; q < N; ++q)
         if (q != j) {
-          const R cjq = (k.sigN[j] * ct[j] - k.sigN[q] * ct[q]) * k.inv_sig[j][q];
+          const D cjq = (k.sigN[j] * ct[j] - k.sigN[q] * ct[q]) * k.inv_sig[j][q];
           acc += cjq * C[j] * C[q];
         }
       W[j] = acc;
     }
 #pragma unroll
     for (int i = 0; i < N; ++i) {
-      R bulk = R(0), grad = R(0), wet = R(0);
-      const R gi = gprime(C[i]);
+      D bulk = D(0), grad = D(0), wet = D(0);
+      const D gi = gprime(C[i]);
 #pragma unroll
       for (int j = 0; j < N; ++j) {
         if (j != i) {
@@ -252,34 +243,38 @@ struct Step2D {
           wet += k.wet3[i][j] * W[j];
         }
       }
-      const R pm = psi * bulk + grad + wet * agp;
+      const D pm = psi * bulk + grad + wet * agp;
       psimu_out[i] = pm;
       sm.mu[i][my][mx] = pm / psih;
     }
     if constexpr (MODE != MODE_INIT) sm.T[my][mx] = ld<S, R>(b.TA + idx);
   }
 
-  __device__ static void run(const Coef<R>& k, const Bufs<S>& b) {
+  __device__ static void run(const Coef<D>& kd, const Coef<R>& k,
+                             const Bufs<S>& b) {
     __shared__ Smem sm;
     const int tid = threadIdx.x;
     const int tx = tid % TX, ty = tid / TX;
     const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
 
-    R psiC[N], psimu[N], dummy[N];
-    node1(sm, k, b, x0, y0, tx + 2, ty + 2, psiC);
+    D psiC[N], psimu_d[N], dummy[N];
+    node1(sm, kd, b, x0, y0, tx + 2, ty + 2, psiC);
     for (int r = tid; r < RING1; r += NT) {
       int lx, ly;
       ring1(r, lx, ly);
-      node1(sm, k, b, x0, y0, lx, ly, dummy);
+      node1(sm, kd, b, x0, y0, lx, ly, dummy);
     }
     __syncthreads();
-    node2(sm, k, b, x0, y0, tx + 1, ty + 1, psimu);
+    node2(sm, kd, b, x0, y0, tx + 1, ty + 1, psimu_d);
     for (int r = tid; r < RING2; r += NT) {
       int mx, my;
       ring2(r, mx, my);
-      node2(sm, k, b, x0, y0, mx, my, dummy);
+      node2(sm, kd, b, x0, y0, mx, my, dummy);
     }
     __syncthreads();
+    R psimu[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) psimu[i] = R(psimu_d[i]);
 
     const int gx = x0 + tx, gy = y0 + ty;
     if (gx >= k.nx || gy >= k.ny) return;
@@ -288,24 +283,24 @@ struct Step2D {
     const int lx = tx + 2, ly = ty + 2, mx = tx + 1, my = ty + 1;
 
     // ---- gradients from LDS -------------------------------------------
-    const Patch<R> ps = patch(sm.psi, lx, ly);
-    const R psi = ps.v[1][1];
-    const R psih = psi > k.psi_min ? psi : k.psi_min;
-    const R gpsi[2] = {grad_x(ps), grad_y(ps)};
-    const Patch<R> pr = patch(sm.prho, lx, ly);
-    const R psirho = pr.v[1][1];
-    const R gprho[2] = {grad_x(pr), grad_y(pr)};
+    const Patch<D> ps = patch(sm.psi, lx, ly);
+    const R psi = R(ps.v[1][1]);
+    const D psih_d = ps.v[1][1] > kd.psi_min ? ps.v[1][1] : kd.psi_min;
+    const R gpsi[2] = {R(grad_x(ps)), R(grad_y(ps))};
+    const Patch<D> pr = patch(sm.prho, lx, ly);
+    const R psirho = R(pr.v[1][1]);
+    const R gprho[2] = {R(grad_x(pr)), R(grad_y(pr))};
     R C[N], gC[N][2], mu[N], gmu[N][2];
 #pragma unroll
     for (int i = 0; i < N; ++i) {
-      const Patch<R> cp = patch(sm.C[i], lx, ly);
-      C[i] = cp.v[1][1];
-      gC[i][0] = grad_x(cp);
-      gC[i][1] = grad_y(cp);
-      const Patch<R> mp = patch(sm.mu[i], mx, my);
-      mu[i] = mp.v[1][1];
-      gmu[i][0] = grad_x(mp);
-      gmu[i][1] = grad_y(mp);
+      const Patch<D> cp = patch(sm.C[i], lx, ly);
+      C[i] = R(cp.v[1][1]);
+      gC[i][0] = R(grad_x(cp));
+      gC[i][1] = R(grad_y(cp));
+      const Patch<D> mp = patch(sm.mu[i], mx, my);
+      mu[i] = R(mp.v[1][1]);
+      gmu[i][0] = R(grad_x(mp));
+      gmu[i][1] = R(grad_y(mp));
     }
     R grho[2] = {R(0), R(0)};
 #pragma unroll
@@ -403,7 +398,7 @@ struct Step2D {
       const R ugpr = u[0] * gprho[0] + u[1] * gprho[1];
       psiP = k.pref * (sum_gm + k.cgr * psi * ugr + k.halfK * (dtY[0] + dtY[2]) +
                        k.KH * (s21 - R(2)) / s21 * ugpr + s0eq);
-      P = psiP / psih;
+      P = R(D(psiP) / psih_d);
     }
 
     if constexpr (MODE == MODE_MOMENTS) {
@@ -471,7 +466,7 @@ struct Step2D {
     // ---- phase sets: equilibrium (3.5), source (3.6, 3.7), collision ---
 #pragma unroll
     for (int i = 0; i < N; ++i) {
-      const R X[2] = {psiC[i] * u[0], psiC[i] * u[1]};
+      const R X[2] = {R(psiC[i]) * u[0], R(psiC[i]) * u[1]};
       R V[2] = {R(0), R(0)};
       if constexpr (MODE != MODE_INIT) {
         // S_i = psi [(C_i sum_{j!=i} C_j - 1) grad mu_i
@@ -496,11 +491,15 @@ struct Step2D {
       const S* fsrc = b.fA + (long long)i * Q * n;
       S* fdst = b.fB + (long long)i * Q * n;
       R fp[Q];
+      // rest population in float64: f^eq_0 = (w_0 - 1) eta phi mu + phi C
+      const D feq0 = (kd.wf[0] - D(1)) * kd.eta[i] * psimu_d[i] + psiC[i];
+      D f0 = D(0);
+      if constexpr (MODE != MODE_INIT) f0 = b.f0A[i * n + idx];
+      d[0] = R(f0 - feq0);
 #pragma unroll
-      for (int p = 0; p < Q; ++p) {
+      for (int p = 1; p < Q; ++p) {
         const int cx = D2Q9::c[p].x, cy = D2Q9::c[p].y;
-        R feq = k.wf[p] * (em + (R(cx) * X[0] + R(cy) * X[1]) * k.inv_cs2);
-        if (p == 0) feq = (k.wf[0] - R(1)) * em + psiC[i];
+        const R feq = k.wf[p] * (em + (R(cx) * X[0] + R(cy) * X[1]) * k.inv_cs2);
         if constexpr (MODE == MODE_INIT) {
           d[p] = feq;
         } else {
@@ -509,8 +508,9 @@ struct Step2D {
         }
       }
       if constexpr (MODE == MODE_INIT) {
+        b.f0B[i * n + idx] = feq0;
 #pragma unroll
-        for (int p = 0; p < Q; ++p)
+        for (int p = 1; p < Q; ++p)
           fdst[p * n + nb.src(D2Q9::c[p].x, D2Q9::c[p].y)] = S(d[p]);
       } else {
         R Fs[Q];
@@ -528,8 +528,9 @@ struct Step2D {
           ms[q] = s * m[q] - (R(1) - R(0.5) * s) * mf[q];
         }
         from_hermite<D2Q9>(ms, del, k.cs2);
+        b.f0B[i * n + idx] = f0 - D(del[0]);
 #pragma unroll
-        for (int p = 0; p < Q; ++p) fdst[p * n + idx] = S(fp[p] - del[p]);
+        for (int p = 1; p < Q; ++p) fdst[p * n + idx] = S(fp[p] - del[p]);
       }
       b.hist[(2 * i) * n + idx] = S(X[0]);
       b.hist[(2 * i + 1) * n + idx] = S(X[1]);
@@ -542,30 +543,31 @@ struct Step2D {
 };
 
 template <int N, class S, class R, int MODE, int TY>
-__global__ __launch_bounds__(TX* TY) void k_step2d(Coef<R> k, Bufs<S> b) {
-  Step2D<N, S, R, MODE, TY>::run(k, b);
+__global__ __launch_bounds__(TX* TY) void k_step2d(Coef<double> kd, Coef<R> k,
+                                                    Bufs<S> b) {
+  Step2D<N, S, R, MODE, TY>::run(kd, k, b);
 }
 
 template <int N, class S, class R, int MODE>
-hipError_t launch_ty(const Coef<R>& k, const Bufs<S>& b, int ty,
-                     hipStream_t st) {
+hipError_t launch_ty(const Coef<double>& kd, const Coef<R>& k,
+                     const Bufs<S>& b, int ty, hipStream_t st) {
   switch (ty) {
     case 4: {
       dim3 g((k.nx + TX - 1) / TX, (k.ny + 3) / 4);
       hipLaunchKernelGGL((k_step2d<N, S, R, MODE, 4>), g, dim3(TX * 4), 0, st,
-                         k, b);
+                         kd, k, b);
       break;
     }
     case 2: {
       dim3 g((k.nx + TX - 1) / TX, (k.ny + 1) / 2);
       hipLaunchKernelGGL((k_step2d<N, S, R, MODE, 2>), g, dim3(TX * 2), 0, st,
-                         k, b);
+                         kd, k, b);
       break;
     }
     default: {
       dim3 g((k.nx + TX - 1) / TX, (k.ny + 7) / 8);
       hipLaunchKernelGGL((k_step2d<N, S, R, MODE, 8>), g, dim3(TX * 8), 0, st,
-                         k, b);
+                         kd, k, b);
       break;
     }
   }
@@ -573,39 +575,42 @@ hipError_t launch_ty(const Coef<R>& k, const Bufs<S>& b, int ty,
 }
 
 template <int N, class S, class R>
-hipError_t launch_mode(int mode, const Coef<R>& k, const Bufs<S>& b, int ty,
-                       hipStream_t st) {
+hipError_t launch_mode(int mode, const Coef<double>& kd, const Coef<R>& k,
+                       const Bufs<S>& b, int ty, hipStream_t st) {
   switch (mode) {
     case MODE_STEP:
-      return launch_ty<N, S, R, MODE_STEP>(k, b, ty, st);
+      return launch_ty<N, S, R, MODE_STEP>(kd, k, b, ty, st);
     case MODE_INIT:
-      return launch_ty<N, S, R, MODE_INIT>(k, b, ty, st);
+      return launch_ty<N, S, R, MODE_INIT>(kd, k, b, ty, st);
     default:
-      return launch_ty<N, S, R, MODE_MOMENTS>(k, b, ty, st);
+      return launch_ty<N, S, R, MODE_MOMENTS>(kd, k, b, ty, st);
   }
 }
 
 }  // namespace
 
 template <class S, class R>
-hipError_t launch_2d(int nphase, int mode, const Coef<R>& k, const Bufs<S>& b,
-                     int ty, hipStream_t st) {
+hipError_t launch_2d(int nphase, int mode, const Coef<double>& kd,
+                     const Coef<R>& k, const Bufs<S>& b, int ty,
+                     hipStream_t st) {
   switch (nphase) {
     case 2:
-      return launch_mode<2, S, R>(mode, k, b, ty, st);
+      return launch_mode<2, S, R>(mode, kd, k, b, ty, st);
     case 3:
-      return launch_mode<3, S, R>(mode, k, b, ty, st);
+      return launch_mode<3, S, R>(mode, kd, k, b, ty, st);
     case 4:
-      return launch_mode<4, S, R>(mode, k, b, ty, st);
+      return launch_mode<4, S, R>(mode, kd, k, b, ty, st);
     default:
       return hipErrorInvalidValue;
   }
 }
 
 template hipError_t launch_2d<double, double>(int, int, const Coef<double>&,
+                                              const Coef<double>&,
                                               const Bufs<double>&, int,
                                               hipStream_t);
-template hipError_t launch_2d<float, float>(int, int, const Coef<float>&,
+template hipError_t launch_2d<float, float>(int, int, const Coef<double>&,
+                                            const Coef<float>&,
                                             const Bufs<float>&, int,
                                             hipStream_t);
 

@@ -1,23 +1,720 @@
-// 3D step kernels (D3Q15 phase sets, D3Q19 flow set).
+// Fused 3D DD-CCLB step for gfx950: D3Q15 phase sets, D3Q19 flow set.
+//
+// 2.5-D tiling: a workgroup owns a TX x TY column of nodes (TX = 64, one
+// wavefront per row) and marches up a block of ZB planes. Rolling LDS
+// windows hold, per plane, the volume fractions C_i and psi on the tile plus
+// a 2-node xy halo (4 planes), the chemical potentials mu_i on the tile plus
+// a 1-node halo (3 planes) and the lagged flux tensor T (3 planes). Every
+// z-iteration computes one new C plane, one new mu plane and one plane of
+// output nodes, so each plane's C and mu are evaluated once per workgroup
+// column (plus the 2-plane ramp at each end of the block).
+//
+// Per output node the work is that of the 2D kernel with three components
+// (Section 3): gradients from LDS, mobility terms (eqs. 2.5, 3.7), force and
+// implicit-penalty velocity (eq. 3.13), pressure (eq. 19 with the 3D
+// constants), equilibria and sources (eqs. 3.5-3.12), Hermite collision
+// (eqs. 3.1-3.4) with compile-time moment tables, and pull streaming.
+//
+// Storage as in 2D: float64 rest populations of the phase sets in their own
+// plane, g_0 stored as g_0 - rho0, history phi C_i u (3N), Y (6), P in place,
+// T (xy, xz, yz) double-buffered. C, mu and psi rho are evaluated in float64.
 #include <hip/hip_runtime.h>
 
 #include "coef.hpp"
+#include "common.hpp"
 #include "kernels.hpp"
+#include "lattice.hpp"
 
 namespace ddcc {
 
-bool have_3d() { return false; }
+bool have_3d() { return true; }
+
+namespace {
+
+constexpr int TX = 64;
+
+// 3x3x3 neighbourhood [dz+1][dy+1][dx+1]; the 8 corners are not used by the
+// D3Q19-weight stencil.
+template <class T>
+struct Patch3 {
+  T v[3][3][3];
+};
+
+// Fixed isotropic stencil: D3Q19 weights at d0 = 1/3 (1/18 faces, 1/36
+// edges) divided by c_s^2 = 1/3, i.e. 1/6 on faces and 1/12 on edges.
+template <int q>
+constexpr double stencil_w() {
+  return (D3Q19::c[q].x * D3Q19::c[q].x + D3Q19::c[q].y * D3Q19::c[q].y +
+          D3Q19::c[q].z * D3Q19::c[q].z) == 1
+             ? 1.0 / 6.0
+             : 1.0 / 12.0;
+}
+
+template <class T, int a, int q>
+__device__ inline void grad_term(T& s, const Patch3<T>& p) {
+  constexpr int cx = D3Q19::c[q].x, cy = D3Q19::c[q].y, cz = D3Q19::c[q].z;
+  constexpr int comp = a == 0 ? cx : (a == 1 ? cy : cz);
+  if constexpr (comp != 0)
+    s += T(comp * stencil_w<q>()) * p.v[cz + 1][cy + 1][cx + 1];
+}
+
+template <class T, int a, int... q>
+__device__ inline T grad_impl(const Patch3<T>& p,
+                              std::integer_sequence<int, q...>) {
+  T s = T(0);
+  (grad_term<T, a, q + 1>(s, p), ...);
+  return s;
+}
+
+template <int a, class T>
+__device__ inline T grad3(const Patch3<T>& p) {
+  return grad_impl<T, a>(p, std::make_integer_sequence<int, 18>{});
+}
+
+template <class T, int q>
+__device__ inline void lap_term(T& s, const Patch3<T>& ps, const Patch3<T>& c) {
+  constexpr int cx = D3Q19::c[q].x, cy = D3Q19::c[q].y, cz = D3Q19::c[q].z;
+  s += T(stencil_w<q>()) * (ps.v[cz + 1][cy + 1][cx + 1] + ps.v[1][1][1]) *
+       (c.v[cz + 1][cy + 1][cx + 1] - c.v[1][1][1]);
+}
+
+template <class T, int... q>
+__device__ inline T lap_impl(const Patch3<T>& ps, const Patch3<T>& c,
+                             std::integer_sequence<int, q...>) {
+  T s = T(0);
+  (lap_term<T, q + 1>(s, ps, c), ...);
+  return s;
+}
+
+// div(psi grad C) in conservative two-point-flux form (eq. 2.14 term).
+template <class T>
+__device__ inline T div_psi_grad3(const Patch3<T>& ps, const Patch3<T>& c) {
+  return lap_impl(ps, c, std::make_integer_sequence<int, 18>{});
+}
+
+struct Nbr3 {
+  int xm, xp, ym, yp, zm, zp, x, y, z, nx, ny;
+  // pull: population with velocity c at (x, y, z) comes from x - c
+  __device__ inline long long src(int cx, int cy, int cz) const {
+    const int sx = cx == 1 ? xm : (cx == -1 ? xp : x);
+    const int sy = cy == 1 ? ym : (cy == -1 ? yp : y);
+    const int sz = cz == 1 ? zm : (cz == -1 ? zp : z);
+    return ((long long)sz * ny + sy) * nx + sx;
+  }
+};
+
+__device__ inline Nbr3 make_nbr3(int gx, int gy, int gz, int nx, int ny,
+                                 int nz) {
+  Nbr3 b;
+  b.x = gx;
+  b.y = gy;
+  b.z = gz;
+  b.nx = nx;
+  b.ny = ny;
+  b.xm = gx == 0 ? nx - 1 : gx - 1;
+  b.xp = gx == nx - 1 ? 0 : gx + 1;
+  b.ym = gy == 0 ? ny - 1 : gy - 1;
+  b.yp = gy == ny - 1 ? 0 : gy + 1;
+  b.zm = gz == 0 ? nz - 1 : gz - 1;
+  b.zp = gz == nz - 1 ? 0 : gz + 1;
+  return b;
+}
+
+template <int N, class LF, class LG, class S, class R, int MODE, int TY, int ZB>
+struct Step3D {
+  using D = double;
+  static constexpr int QF = LF::Q, QG = LG::Q;
+  static constexpr int NT = TX * TY;
+  static constexpr int HX = TX + 4, HY = TY + 4;  // C region (xy halo 2)
+  static constexpr int MX = TX + 2, MY = TY + 2;  // mu region (xy halo 1)
+  static constexpr int NCP = 4, NMP = 3;          // window depths
+
+  struct Smem {
+    D C[NCP][N][HY][HX];
+    S psi[NCP][HY][HX];
+    D mu[NMP][N][MY][MX];
+    R T[NMP][3][MY][MX];
+  };
+
+  __device__ static inline int slot(int z, int m) {
+    const int r = z % m;
+    return r < 0 ? r + m : r;
+  }
+
+  // C plane z at region coordinates (lx, ly)
+  __device__ static inline void node1(Smem& sm, const Coef<D>& k,
+                                      const Bufs<S>& b, int x0, int y0, int z,
+                                      int lx, int ly) {
+    const int gx = wrap(x0 + lx - 2, k.nx), gy = wrap(y0 + ly - 2, k.ny);
+    const int gz = wrap(z, k.nz);
+    const long long idx = ((long long)gz * k.ny + gy) * k.nx + gx;
+    const S psiS = b.psi[idx];
+    const D psi = D(psiS);
+    D psiC[N];
+    if constexpr (MODE == MODE_INIT) {
+#pragma unroll
+      for (int i = 0; i < N; ++i) psiC[i] = psi * b.inC[i * k.n + idx];
+    } else {
+      const Nbr3 nb = make_nbr3(gx, gy, gz, k.nx, k.ny, k.nz);
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        const S* f = b.fA + (long long)i * QF * k.n;
+        D s = b.f0A[i * k.n + idx];
+#pragma unroll
+        for (int p = 1; p < QF; ++p)
+          s += ld<S, D>(f + p * k.n + nb.src(LF::c[p].x, LF::c[p].y, LF::c[p].z));
+        psiC[i] = s;
+      }
+    }
+    // C_i = phi C_i / sum_j phi C_j (keeps sum_j C_j = 1 exact)
+    D tot = D(0);
+#pragma unroll
+    for (int i = 0; i < N; ++i) tot += psiC[i];
+    const D inv = D(1) / (tot > k.psi_min ? tot : k.psi_min);
+    const int s4 = slot(z, NCP);
+#pragma unroll
+    for (int i = 0; i < N; ++i) sm.C[s4][i][ly][lx] = psiC[i] * inv;
+    sm.psi[s4][ly][lx] = psiS;
+  }
+
+  __device__ static inline Patch3<D> cpatch(const Smem& sm, int i, int z,
+                                            int lx, int ly) {
+    Patch3<D> p;
+#pragma unroll
+    for (int dz = -1; dz <= 1; ++dz) {
+      const int s4 = slot(z + dz, NCP);
+#pragma unroll
+      for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+        for (int dx = -1; dx <= 1; ++dx)
+          p.v[dz + 1][dy + 1][dx + 1] =
+              (dx != 0 && dy != 0 && dz != 0)
+                  ? D(0)
+                  : sm.C[s4][i][ly + dy][lx + dx];
+    }
+    return p;
+  }
+
+  __device__ static inline Patch3<D> psipatch(const Smem& sm, int z, int lx,
+                                              int ly) {
+    Patch3<D> p;
+#pragma unroll
+    for (int dz = -1; dz <= 1; ++dz) {
+      const int s4 = slot(z + dz, NCP);
+#pragma unroll
+      for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+        for (int dx = -1; dx <= 1; ++dx)
+          p.v[dz + 1][dy + 1][dx + 1] =
+              (dx != 0 && dy != 0 && dz != 0)
+                  ? D(0)
+                  : D(sm.psi[s4][ly + dy][lx + dx]);
+    }
+    return p;
+  }
+
+  // mu plane z at mu-region coordinates (mx, my): phi mu_i (eq. 2.14)
+  __device__ static inline void node2(Smem& sm, const Coef<D>& k,
+                                      const Bufs<S>& b, int x0, int y0, int z,
+                                      int mx, int my) {
+    const int lx = mx + 1, ly = my + 1;
+    const int gx = wrap(x0 + mx - 1, k.nx), gy = wrap(y0 + my - 1, k.ny);
+    const int gz = wrap(z, k.nz);
+    const long long idx = ((long long)gz * k.ny + gy) * k.nx + gx;
+    const Patch3<D> ps = psipatch(sm, z, lx, ly);
+    const D psi = ps.v[1][1][1];
+    const D psih = psi > k.psi_min ? psi : k.psi_min;
+    const D g0 = grad3<0>(ps), g1 = grad3<1>(ps), g2 = grad3<2>(ps);
+    const D agp = sqrt(g0 * g0 + g1 * g1 + g2 * g2);
+    D C[N], L[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      const Patch3<D> cp = cpatch(sm, j, z, lx, ly);
+      C[j] = cp.v[1][1][1];
+      L[j] = div_psi_grad3(ps, cp);
+    }
+    D ct[N];
+#pragma unroll
+    for (int i = 0; i < N - 1; ++i) ct[i] = ld<S, D>(b.ct + i * k.n + idx);
+    ct[N - 1] = D(0);
+    D W[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      D acc = D(0);
+#pragma unroll
+      for (int q = 0; q < N; ++q)
+        if (q != j) {
+          const D cjq = (k.sigN[j] * ct[j] - k.sigN[q] * ct[q]) * k.inv_sig[j][q];
+          acc += cjq * C[j] * C[q];
+        }
+      W[j] = acc;
+    }
+    const int s3 = slot(z, NMP);
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      D bulk = D(0), grad = D(0), wet = D(0);
+      const D gi = gprime(C[i]);
+#pragma unroll
+      for (int j = 0; j < N; ++j)
+        if (j != i) {
+          bulk += k.beta2[i][j] * (gi - gprime(C[i] + C[j]));
+          grad += k.grad34[i][j] * L[j];
+          wet += k.wet3[i][j] * W[j];
+        }
+      sm.mu[s3][i][my][mx] = (psi * bulk + grad + wet * agp) / psih;
+    }
+    if constexpr (MODE != MODE_INIT) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+        sm.T[s3][c][my][mx] = ld<S, R>(b.TA + c * k.n + idx);
+    }
+  }
+
+  __device__ static inline Patch3<D> mupatch(const Smem& sm, int i, int z,
+                                             int mx, int my) {
+    Patch3<D> p;
+#pragma unroll
+    for (int dz = -1; dz <= 1; ++dz) {
+      const int s3 = slot(z + dz, NMP);
+#pragma unroll
+      for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+        for (int dx = -1; dx <= 1; ++dx)
+          p.v[dz + 1][dy + 1][dx + 1] =
+              (dx != 0 && dy != 0 && dz != 0)
+                  ? D(0)
+                  : sm.mu[s3][i][my + dy][mx + dx];
+    }
+    return p;
+  }
+
+  __device__ static inline Patch3<R> tpatch(const Smem& sm, int c, int z,
+                                            int mx, int my) {
+    Patch3<R> p;
+#pragma unroll
+    for (int dz = -1; dz <= 1; ++dz) {
+      const int s3 = slot(z + dz, NMP);
+#pragma unroll
+      for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+        for (int dx = -1; dx <= 1; ++dx)
+          p.v[dz + 1][dy + 1][dx + 1] =
+              (dx != 0 && dy != 0 && dz != 0)
+                  ? R(0)
+                  : sm.T[s3][c][my + dy][mx + dx];
+    }
+    return p;
+  }
+
+  // Output node (tx, ty) of plane z.
+  __device__ static inline void node3(const Smem& sm, const Coef<D>& kd,
+                                      const Coef<R>& k, const Bufs<S>& b,
+                                      int x0, int y0, int z, int tx, int ty) {
+    const int gx = x0 + tx, gy = y0 + ty;
+    const long long n = k.n;
+    const long long idx = ((long long)z * k.ny + gy) * k.nx + gx;
+    const int lx = tx + 2, ly = ty + 2, mx = tx + 1, my = ty + 1;
+    const Nbr3 nb = make_nbr3(gx, gy, z, k.nx, k.ny, k.nz);
+
+    const Patch3<D> ps = psipatch(sm, z, lx, ly);
+    const D psi_d = ps.v[1][1][1];
+    const R psi = R(psi_d);
+    const D psih_d = psi_d > kd.psi_min ? psi_d : kd.psi_min;
+    const R gpsi[3] = {R(grad3<0>(ps)), R(grad3<1>(ps)), R(grad3<2>(ps))};
+    // phi rho on the patch from C and psi
+    Patch3<D> pr;
+#pragma unroll
+    for (int a = 0; a < 27; ++a) (&pr.v[0][0][0])[a] = D(0);
+    R C[N], gC[N][3], mu[N], gmu[N][3];
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      const Patch3<D> cp = cpatch(sm, i, z, lx, ly);
+#pragma unroll
+      for (int a = 0; a < 27; ++a)
+        (&pr.v[0][0][0])[a] += kd.rho[i] * (&cp.v[0][0][0])[a];
+      C[i] = R(cp.v[1][1][1]);
+      gC[i][0] = R(grad3<0>(cp));
+      gC[i][1] = R(grad3<1>(cp));
+      gC[i][2] = R(grad3<2>(cp));
+      const Patch3<D> mp = mupatch(sm, i, z, mx, my);
+      mu[i] = R(mp.v[1][1][1]);
+      gmu[i][0] = R(grad3<0>(mp));
+      gmu[i][1] = R(grad3<1>(mp));
+      gmu[i][2] = R(grad3<2>(mp));
+    }
+#pragma unroll
+    for (int a = 0; a < 27; ++a) (&pr.v[0][0][0])[a] *= (&ps.v[0][0][0])[a];
+    const R psirho = R(pr.v[1][1][1]);
+    const R gprho[3] = {R(grad3<0>(pr)), R(grad3<1>(pr)), R(grad3<2>(pr))};
+    R grho[3] = {R(0), R(0), R(0)};
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+      for (int a = 0; a < 3; ++a) grho[a] += k.rho[i] * gC[i][a];
+
+    // own phi C_i (sum of the pulled populations) and phi mu_i = mu_i psi
+    D psiC[N];
+    R fp[N][QF];
+    D f0[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      if constexpr (MODE == MODE_INIT) {
+        psiC[i] = psi_d * b.inC[i * n + idx];
+      } else {
+        const S* f = b.fA + (long long)i * QF * n;
+        f0[i] = b.f0A[i * n + idx];
+        D s = f0[i];
+#pragma unroll
+        for (int p = 1; p < QF; ++p) {
+          fp[i][p] = ld<S, R>(f + p * n + nb.src(LF::c[p].x, LF::c[p].y, LF::c[p].z));
+          s += D(fp[i][p]);
+        }
+        psiC[i] = s;
+      }
+    }
+    D psimu_d[N];
+    R psimu[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      psimu_d[i] = D(mu[i]) * psih_d;
+      psimu[i] = R(psimu_d[i]);
+    }
+    // mass flux m^C (eq. 2.5, Section 2.2)
+    R mC[3] = {R(0), R(0), R(0)};
+    R Cs[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      R s = R(0), sr = R(0);
+#pragma unroll
+      for (int q = 0; q < N; ++q)
+        if (q != j) {
+          s += C[q];
+          sr += C[q] * (k.rho[j] - k.rho[q]);
+        }
+      Cs[j] = s;
+      const R aa = k.m0 * C[j] * sr;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) mC[a] -= aa * gmu[j][a];
+    }
+
+    R u[3], F[3] = {R(0), R(0), R(0)};
+    R gp[QG];
+    R sum_gm = R(0);
+    if constexpr (MODE == MODE_INIT) {
+#pragma unroll
+      for (int a = 0; a < 3; ++a) u[a] = b.inU ? R(b.inU[a * n + idx]) : R(0);
+    } else {
+      R j[3] = {R(0), R(0), R(0)};
+#pragma unroll
+      for (int p = 0; p < QG; ++p) {
+        gp[p] = ld<S, R>(b.gA + p * n + nb.src(LG::c[p].x, LG::c[p].y, LG::c[p].z));
+        if (p > 0) sum_gm += gp[p];
+        if (LG::c[p].x) j[0] += R(LG::c[p].x) * gp[p];
+        if (LG::c[p].y) j[1] += R(LG::c[p].y) * gp[p];
+        if (LG::c[p].z) j[2] += R(LG::c[p].z) * gp[p];
+      }
+      // -div T^{n-1} with T antisymmetric, components xy, xz, yz
+      const Patch3<R> txy = tpatch(sm, 0, z, mx, my);
+      const Patch3<R> txz = tpatch(sm, 1, z, mx, my);
+      const Patch3<R> tyz = tpatch(sm, 2, z, mx, my);
+      const R divT[3] = {-grad3<1>(txy) - grad3<2>(txz),
+                         grad3<0>(txy) - grad3<2>(tyz),
+                         grad3<0>(txz) + grad3<1>(tyz)};
+      const R Pprev = ld<S, R>(b.hist + (3 * N + 6) * n + idx);
+      R Fp[3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        Fp[a] = -divT[a] + Pprev * gpsi[a] + psirho * k.accel[a] +
+                psi * k.force[a];
+#pragma unroll
+        for (int i = 0; i < N; ++i) Fp[a] += psimu[i] * gC[i][a];
+      }
+      const R pen = (R(1) - psi) * k.lam;
+      const R den = R(1) / (psirho + R(0.5) * pen);
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        u[a] = (j[a] + R(0.5) * Fp[a]) * den;
+        F[a] = Fp[a] - pen * u[a];
+      }
+    }
+
+    // Y = sym(phi m^C u): xx, xy, xz, yy, yz, zz; T = antisym: xy, xz, yz
+    const R Y[6] = {psi * mC[0] * u[0],
+                    R(0.5) * psi * (mC[0] * u[1] + u[0] * mC[1]),
+                    R(0.5) * psi * (mC[0] * u[2] + u[0] * mC[2]),
+                    psi * mC[1] * u[1],
+                    R(0.5) * psi * (mC[1] * u[2] + u[1] * mC[2]),
+                    psi * mC[2] * u[2]};
+    const R Tn[3] = {R(0.5) * psi * (mC[0] * u[1] - u[0] * mC[1]),
+                     R(0.5) * psi * (mC[0] * u[2] - u[0] * mC[2]),
+                     R(0.5) * psi * (mC[1] * u[2] - u[1] * mC[2])};
+    R dtY[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
+    if constexpr (MODE != MODE_INIT) {
+#pragma unroll
+      for (int q = 0; q < 6; ++q)
+        dtY[q] = Y[q] - ld<S, R>(b.hist + (3 * N + q) * n + idx);
+    }
+    R nu = R(0);
+#pragma unroll
+    for (int i = 0; i < N; ++i) nu += k.nu[i] * C[i];
+    const R s21 = R(1) / (k.two_over_c2mcs2 * nu + R(0.5));
+    const R s22 = R(1) / (k.inv_cs2 * nu + R(0.5));
+    // A = phi rho u u + Y, index map as Y
+    const R A[6] = {psirho * u[0] * u[0] + Y[0], psirho * u[0] * u[1] + Y[1],
+                    psirho * u[0] * u[2] + Y[2], psirho * u[1] * u[1] + Y[3],
+                    psirho * u[1] * u[2] + Y[4], psirho * u[2] * u[2] + Y[5]};
+    R psiP, P;
+    if constexpr (MODE == MODE_INIT) {
+      P = b.inP ? R(b.inP[idx]) : R(0);
+      psiP = psi * P;
+    } else {
+      const R s0eq = -k.wg[0] * (A[0] + A[3] + A[5]) * k.inv_c2mcs2;
+      const R ugr = u[0] * grho[0] + u[1] * grho[1] + u[2] * grho[2];
+      const R ugpr = u[0] * gprho[0] + u[1] * gprho[1] + u[2] * gprho[2];
+      psiP = k.pref * (sum_gm + k.cgr * psi * ugr +
+                       k.halfK * (dtY[0] + dtY[3] + dtY[5]) +
+                       k.KH * (s21 - R(2)) / s21 * ugpr + s0eq);
+      P = R(D(psiP) / psih_d);
+    }
+    const R uvec[3] = {u[0], u[1], u[2]};
+    if constexpr (MODE == MODE_MOMENTS) {
+#pragma unroll
+      for (int i = 0; i < N; ++i) b.outC[i * n + idx] = double(C[i]);
+#pragma unroll
+      for (int a = 0; a < 3; ++a) b.outU[a * n + idx] = double(uvec[a]);
+      b.outP[idx] = double(P);
+      return;
+    }
+
+    // ---- flow set ------------------------------------------------------
+    {
+      R d[QG];
+#pragma unroll
+      for (int p = 0; p < QG; ++p) {
+        const int cx = LG::c[p].x, cy = LG::c[p].y, cz = LG::c[p].z;
+        const R h2 = (A[0] * (R(cx * cx) - k.cs2) + A[3] * (R(cy * cy) - k.cs2) +
+                      A[5] * (R(cz * cz) - k.cs2)) *
+                         k.h2diag +
+                     (A[1] * R(cx * cy) + A[2] * R(cx * cz) + A[4] * R(cy * cz)) *
+                         k.h2off;
+        R geq = k.wg[p] * ((psiP + psirho * (R(cx) * u[0] + R(cy) * u[1] +
+                                               R(cz) * u[2])) *
+                               k.inv_cs2 +
+                           h2);
+        if (p == 0) geq -= psiP * k.inv_cs2;  // stored as g_0 - rho0
+        if constexpr (MODE == MODE_INIT) {
+          d[p] = geq;
+        } else {
+          d[p] = gp[p] - geq;
+        }
+      }
+      if constexpr (MODE == MODE_INIT) {
+#pragma unroll
+        for (int p = 0; p < QG; ++p)
+          b.gB[p * n + nb.src(LG::c[p].x, LG::c[p].y, LG::c[p].z)] = S(d[p]);
+      } else {
+        const R ub = u[0] * gprho[0] + u[1] * gprho[1] + u[2] * gprho[2];
+        // M^{2G} (eq. 3.12) with the scalar u.grad(phi rho) on the diagonal
+        const R M[6] = {
+            dtY[0] + R(2) * k.cs2 * u[0] * gprho[0] + k.one_m3cs2 * ub,
+            dtY[1] + k.cs2 * (u[0] * gprho[1] + gprho[0] * u[1]),
+            dtY[2] + k.cs2 * (u[0] * gprho[2] + gprho[0] * u[2]),
+            dtY[3] + R(2) * k.cs2 * u[1] * gprho[1] + k.one_m3cs2 * ub,
+            dtY[4] + k.cs2 * (u[1] * gprho[2] + gprho[1] * u[2]),
+            dtY[5] + R(2) * k.cs2 * u[2] * gprho[2] + k.one_m3cs2 * ub};
+        const R a0 = psi * (u[0] * grho[0] + u[1] * grho[1] + u[2] * grho[2]);
+        R G[QG];
+#pragma unroll
+        for (int p = 0; p < QG; ++p) {
+          const int cx = LG::c[p].x, cy = LG::c[p].y, cz = LG::c[p].z;
+          const R h2 = (M[0] * (R(cx * cx) - k.cs2) + M[3] * (R(cy * cy) - k.cs2) +
+                        M[5] * (R(cz * cz) - k.cs2)) *
+                           k.h2diag +
+                       (M[1] * R(cx * cy) + M[2] * R(cx * cz) + M[4] * R(cy * cz)) *
+                           k.h2off;
+          G[p] = k.wg[p] * (a0 +
+                            (R(cx) * F[0] + R(cy) * F[1] + R(cz) * F[2]) *
+                                k.inv_cs2 +
+                            h2);
+        }
+        R m[QG], mg[QG], ms[QG], del[QG];
+        to_hermite<LG>(d, m, k.cs2);
+        to_hermite<LG>(G, mg, k.cs2);
+#pragma unroll
+        for (int q = 0; q < QG; ++q) {
+          const int grp = LG::rows[q].group;
+          const R s = grp == GR21 ? s21 : (grp == GR22 ? s22 : k.sg[grp]);
+          ms[q] = s * m[q] - (R(1) - R(0.5) * s) * mg[q];
+        }
+        from_hermite<LG>(ms, del, k.cs2);
+#pragma unroll
+        for (int p = 0; p < QG; ++p) b.gB[p * n + idx] = S(gp[p] - del[p]);
+      }
+    }
+
+    // ---- phase sets ----------------------------------------------------
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      const R X[3] = {R(psiC[i]) * u[0], R(psiC[i]) * u[1], R(psiC[i]) * u[2]};
+      R V[3] = {R(0), R(0), R(0)};
+      if constexpr (MODE != MODE_INIT) {
+        R Sv[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          R sa = (C[i] * Cs[i] - R(1)) * gmu[i][a];
+#pragma unroll
+          for (int j = 0; j < N; ++j)
+            if (j != i) sa -= C[i] * C[j] * gmu[j][a];
+          Sv[a] = psi * sa;
+        }
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          const R dX = X[a] - ld<S, R>(b.hist + (3 * i + a) * n + idx);
+          V[a] = dX + k.cs2 * k.eta[i] * (mu[i] * gpsi[a] - Sv[a]);
+        }
+      }
+      const R em = k.eta[i] * psimu[i];
+      const D feq0 = (kd.wf[0] - D(1)) * kd.eta[i] * psimu_d[i] + psiC[i];
+      R d[QF];
+      S* fdst = b.fB + (long long)i * QF * n;
+      if constexpr (MODE == MODE_INIT) {
+        b.f0B[i * n + idx] = feq0;
+      } else {
+        d[0] = R(f0[i] - feq0);
+      }
+#pragma unroll
+      for (int p = 1; p < QF; ++p) {
+        const int cx = LF::c[p].x, cy = LF::c[p].y, cz = LF::c[p].z;
+        const R feq = k.wf[p] * (em + (R(cx) * X[0] + R(cy) * X[1] + R(cz) * X[2]) *
+                                          k.inv_cs2);
+        if constexpr (MODE == MODE_INIT) {
+          fdst[p * n + nb.src(cx, cy, cz)] = S(feq);
+        } else {
+          d[p] = fp[i][p] - feq;
+        }
+      }
+      if constexpr (MODE != MODE_INIT) {
+        R Fs[QF];
+#pragma unroll
+        for (int p = 0; p < QF; ++p) {
+          const int cx = LF::c[p].x, cy = LF::c[p].y, cz = LF::c[p].z;
+          Fs[p] = k.wf[p] * (R(cx) * V[0] + R(cy) * V[1] + R(cz) * V[2]) *
+                  k.inv_cs2;
+        }
+        R m[QF], mf[QF], ms[QF], del[QF];
+        to_hermite<LF>(d, m, k.cs2);
+        to_hermite<LF>(Fs, mf, k.cs2);
+#pragma unroll
+        for (int q = 0; q < QF; ++q) {
+          const R s = k.sf[LF::rows[q].group];
+          ms[q] = s * m[q] - (R(1) - R(0.5) * s) * mf[q];
+        }
+        from_hermite<LF>(ms, del, k.cs2);
+        b.f0B[i * n + idx] = f0[i] - D(del[0]);
+#pragma unroll
+        for (int p = 1; p < QF; ++p) fdst[p * n + idx] = S(fp[i][p] - del[p]);
+      }
+#pragma unroll
+      for (int a = 0; a < 3; ++a) b.hist[(3 * i + a) * n + idx] = S(X[a]);
+    }
+#pragma unroll
+    for (int q = 0; q < 6; ++q) b.hist[(3 * N + q) * n + idx] = S(Y[q]);
+    b.hist[(3 * N + 6) * n + idx] = S(P);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) b.TB[c * n + idx] = S(Tn[c]);
+  }
+
+  __device__ static void run(const Coef<D>& kd, const Coef<R>& k,
+                             const Bufs<S>& b) {
+    __shared__ Smem sm;
+    const int tid = threadIdx.x;
+    const int tx = tid % TX, ty = tid / TX;
+    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
+    const int z0 = blockIdx.z * ZB;
+    const int z1 = z0 + ZB < k.nz ? z0 + ZB : k.nz;
+    const bool own = (x0 + tx < k.nx) && (y0 + ty < k.ny);
+    for (int zc = z0 - 2; zc <= z1 + 1; ++zc) {
+      for (int r = tid; r < HX * HY; r += NT) {
+        const int ly = r / HX, lx = r - ly * HX;
+        node1(sm, kd, b, x0, y0, zc, lx, ly);
+      }
+      __syncthreads();
+      const int zm = zc - 1;
+      if (zm >= z0 - 1) {
+        for (int r = tid; r < MX * MY; r += NT) {
+          const int my = r / MX, mx = r - my * MX;
+          node2(sm, kd, b, x0, y0, zm, mx, my);
+        }
+      }
+      __syncthreads();
+      const int zo = zc - 2;
+      if (zo >= z0 && own) node3(sm, kd, k, b, x0, y0, zo, tx, ty);
+      __syncthreads();
+    }
+  }
+};
+
+template <int N, class S, class R, int MODE, int TY, int ZB>
+__global__ __launch_bounds__(TX* TY) void k_step3d(Coef<double> kd, Coef<R> k,
+                                                    Bufs<S> b) {
+  Step3D<N, D3Q15, D3Q19, S, R, MODE, TY, ZB>::run(kd, k, b);
+}
+
+constexpr int kZB = 16;
+
+template <int N, class S, class R, int MODE>
+hipError_t launch_3(const Coef<double>& kd, const Coef<R>& k, const Bufs<S>& b,
+                    int ty, hipStream_t st) {
+  const unsigned gx = (k.nx + TX - 1) / TX;
+  const unsigned gz = (k.nz + kZB - 1) / kZB;
+  if (ty == 2) {
+    dim3 g(gx, (k.ny + 1) / 2, gz);
+    hipLaunchKernelGGL((k_step3d<N, S, R, MODE, 2, kZB>), g, dim3(TX * 2), 0,
+                       st, kd, k, b);
+  } else {
+    dim3 g(gx, (k.ny + 3) / 4, gz);
+    hipLaunchKernelGGL((k_step3d<N, S, R, MODE, 4, kZB>), g, dim3(TX * 4), 0,
+                       st, kd, k, b);
+  }
+  return hipGetLastError();
+}
+
+template <int N, class S, class R>
+hipError_t launch_mode3(int mode, const Coef<double>& kd, const Coef<R>& k,
+                        const Bufs<S>& b, int ty, hipStream_t st) {
+  switch (mode) {
+    case MODE_STEP:
+      return launch_3<N, S, R, MODE_STEP>(kd, k, b, ty, st);
+    case MODE_INIT:
+      return launch_3<N, S, R, MODE_INIT>(kd, k, b, ty, st);
+    default:
+      return launch_3<N, S, R, MODE_MOMENTS>(kd, k, b, ty, st);
+  }
+}
+
+}  // namespace
 
 template <class S, class R>
-hipError_t launch_3d(int, int, const Coef<R>&, const Bufs<S>&, int, int,
-                     hipStream_t) {
-  return hipErrorNotSupported;
+hipError_t launch_3d(int nphase, int mode, const Coef<double>& kd,
+                     const Coef<R>& k, const Bufs<S>& b, int tx, int ty,
+                     hipStream_t st) {
+  (void)tx;
+  switch (nphase) {
+    case 2:
+      return launch_mode3<2, S, R>(mode, kd, k, b, ty, st);
+    case 3:
+      return launch_mode3<3, S, R>(mode, kd, k, b, ty, st);
+    default:
+      return hipErrorInvalidValue;
+  }
 }
 
 template hipError_t launch_3d<double, double>(int, int, const Coef<double>&,
+                                              const Coef<double>&,
                                               const Bufs<double>&, int, int,
                                               hipStream_t);
-template hipError_t launch_3d<float, float>(int, int, const Coef<float>&,
+template hipError_t launch_3d<float, float>(int, int, const Coef<double>&,
+                                            const Coef<float>&,
                                             const Bufs<float>&, int, int,
                                             hipStream_t);
 

@@ -15,7 +15,8 @@ constexpr int kWaves = kMassThreads / 64;
 // block through LDS; one partial per block and phase (summed on the host in
 // block order, so the result is deterministic).
 template <class S>
-__global__ __launch_bounds__(kMassThreads) void k_mass(const S* f, int N, int Q,
+__global__ __launch_bounds__(kMassThreads) void k_mass(const double* f0,
+                                                       const S* f, int N, int Q,
                                                        long long n,
                                                        double* partial,
                                                        int* bad) {
@@ -26,8 +27,8 @@ __global__ __launch_bounds__(kMassThreads) void k_mass(const S* f, int N, int Q,
        x += stride) {
     for (int i = 0; i < N; ++i) {
       const S* fi = f + (long long)i * Q * n + x;
-      double s = 0.0;
-      for (int p = 0; p < Q; ++p) {
+      double s = f0[(long long)i * n + x];
+      for (int p = 1; p < Q; ++p) {
         const double v = double(fi[(long long)p * n]);
         s += v;
       }
@@ -69,11 +70,11 @@ __global__ void k_convert(const double* src, S* dst, long long count) {
 }  // namespace
 
 template <class S>
-hipError_t launch_mass(const S* f, int nphase, int Q, long long n,
-                       double* partial, int* bad, int nblocks,
+hipError_t launch_mass(const double* f0, const S* f, int nphase, int Q,
+                       long long n, double* partial, int* bad, int nblocks,
                        hipStream_t st) {
-  hipLaunchKernelGGL((k_mass<S>), dim3(nblocks), dim3(kMassThreads), 0, st, f,
-                     nphase, Q, n, partial, bad);
+  hipLaunchKernelGGL((k_mass<S>), dim3(nblocks), dim3(kMassThreads), 0, st, f0,
+                     f, nphase, Q, n, partial, bad);
   return hipGetLastError();
 }
 
@@ -88,10 +89,12 @@ hipError_t launch_convert(const double* src, S* dst, long long count,
   return hipGetLastError();
 }
 
-template hipError_t launch_mass<double>(const double*, int, int, long long,
-                                        double*, int*, int, hipStream_t);
-template hipError_t launch_mass<float>(const float*, int, int, long long,
-                                       double*, int*, int, hipStream_t);
+template hipError_t launch_mass<double>(const double*, const double*, int,
+                                        int, long long, double*, int*, int,
+                                        hipStream_t);
+template hipError_t launch_mass<float>(const double*, const float*, int, int,
+                                       long long, double*, int*, int,
+                                       hipStream_t);
 template hipError_t launch_convert<double>(const double*, double*, long long,
                                            hipStream_t);
 template hipError_t launch_convert<float>(const double*, float*, long long,

@@ -296,12 +296,17 @@ def unpack_state(sim, buf):
     shape = (ny, nx) if dim == 2 else (nz, ny, nx)
     n = nx * ny * nz
     dt = np.float64 if prec == FP64 else np.float32
-    data = np.frombuffer(bytes(buf[56:]), dtype=dt)
     nhist = N * dim + dim * (dim + 1) // 2 + 1
     nT = dim * (dim - 1) // 2
+    esz = 8 if prec == FP64 else 4
+    raw = bytes(buf[56:])
+    f = np.frombuffer(raw[:N * Qf * n * esz], dtype=dt).reshape(
+        (N, Qf) + shape).astype(np.float64)
+    f0 = np.frombuffer(raw[N * Qf * n * esz:N * Qf * n * esz + N * n * 8],
+                       dtype=np.float64).reshape((N,) + shape)
+    f[:, 0] = f0            # the rest populations live in a float64 plane
+    data = np.frombuffer(raw[N * Qf * n * esz + N * n * 8:], dtype=dt)
     o = 0
-    f = data[o:o + N * Qf * n].reshape((N, Qf) + shape)
-    o += N * Qf * n
     g = data[o:o + Qg * n].reshape((Qg,) + shape)
     o += Qg * n
     hist = data[o:o + nhist * n].reshape((nhist,) + shape)

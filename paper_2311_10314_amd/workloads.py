@@ -217,14 +217,14 @@ def random_small(dim, N, shape, seed, lattice_f=None, lattice_g=None,
     psi = np.ones(shape)
     for _ in range(2):
         c = [rng.uniform(0, n) for n in reversed(shape)]
-        r = rng.uniform(2.0, 0.25 * min(shape))
+        r = rng.uniform(2.0, max(2.5, 0.25 * min(shape)))
         psi = psi * psi_from_distance(periodic_distance(coords, c, shape) - r)
     raw = []
     for _ in range(N):
         acc = np.full(shape, 0.2)
         for _ in range(3):
             c = [rng.uniform(0, n) for n in reversed(shape)]
-            r = rng.uniform(2.0, 0.3 * min(shape))
+            r = rng.uniform(2.0, max(2.5, 0.3 * min(shape)))
             acc = acc + droplet(periodic_distance(coords, c, shape), r, 4.0)
         raw.append(acc)
     raw = np.stack(raw)

@@ -1,0 +1,106 @@
+"""The C ABI library loads, exports every entry point declared in
+include/ddcc.h, and rejects bad parameters before touching a GPU (no GPU
+needed: only host-side calls are made)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ddcc.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ddcc_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2311_10314_amd import ddcc
+    names = declared_functions()
+    assert "ddcc_step" in names and "ddcc_init_geometry" in names
+    lib = ctypes.CDLL(ddcc.LIB_PATH)
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_binding_exposes_the_same_names():
+    from paper_2311_10314_amd import ddcc
+    for n in declared_functions():
+        assert hasattr(ddcc, n), n
+
+
+def test_default_params_and_version():
+    from paper_2311_10314_amd import ddcc
+    p = ddcc.ddcc_params()
+    assert ddcc.ddcc_default_params(ctypes.byref(p)) == ddcc.DDCC_OK
+    assert p.dim == 2 and p.nphase == 2 and p.d0 == 0.4
+    assert abs(p.s_f[1] - 10.0 / 19.0) < 1e-15
+    assert b"gfx950" in ddcc.ddcc_version()
+    assert ddcc.ddcc_default_params(None) == ddcc.DDCC_E_INVAL
+
+
+def _params(**kw):
+    from paper_2311_10314_amd import ddcc
+    p = ddcc.ddcc_params()
+    ddcc.ddcc_default_params(ctypes.byref(p))
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+@pytest.mark.parametrize("field,value", [
+    ("dim", 4), ("nx", 0), ("nz", 3), ("nphase", 1), ("nphase", 5),
+    ("precision", 7), ("d0", 1.0), ("d0", -0.1), ("d0", float("nan")),
+    ("eps", 0.0), ("m0", -1.0), ("psi_min", 0.0), ("lam", -1.0),
+    ("lattice_f", 3),
+])
+def test_create_rejects_bad_scalars(field, value):
+    from paper_2311_10314_amd import ddcc
+    p = _params(**{field: value})
+    h = ctypes.c_void_p()
+    assert ddcc.ddcc_create(ctypes.byref(p), None, ctypes.byref(h)) == \
+        ddcc.DDCC_E_INVAL
+    assert not h.value
+
+
+def test_create_rejects_bad_arrays():
+    from paper_2311_10314_amd import ddcc
+    h = ctypes.c_void_p()
+    p = _params()
+    p.sigma[0][1] = 0.002          # not symmetric
+    assert ddcc.ddcc_create(ctypes.byref(p), None, ctypes.byref(h)) == 1
+    p = _params()
+    p.sigma[1][1] = 0.001          # non-zero diagonal
+    assert ddcc.ddcc_create(ctypes.byref(p), None, ctypes.byref(h)) == 1
+    p = _params()
+    p.s_f[2] = 2.0                 # rate outside (0, 2)
+    assert ddcc.ddcc_create(ctypes.byref(p), None, ctypes.byref(h)) == 1
+    p = _params()
+    p.rho[1] = 0.0
+    assert ddcc.ddcc_create(ctypes.byref(p), None, ctypes.byref(h)) == 1
+    p = _params(d0=0.6, dim=3, nz=8, lattice_f=2, lattice_g=3)
+    # D3Q19 face weight (d0 - 2 d0^2)/2 < 0 at d0 = 0.6
+    assert ddcc.ddcc_create(ctypes.byref(p), None, ctypes.byref(h)) == 1
+
+
+def test_null_context_calls_fail_cleanly():
+    from paper_2311_10314_amd import ddcc
+    assert ddcc.ddcc_step(None, 1) == ddcc.DDCC_E_INVAL
+    assert ddcc.ddcc_sync(None) == ddcc.DDCC_E_INVAL
+    assert ddcc.ddcc_time(None) == -1
+    ddcc.ddcc_destroy(None)
+    assert ddcc.ddcc_last_error(None) == b"NULL context"
+
+
+def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
+    import importlib.util
+    src = os.path.join(ROOT, "paper_2311_10314_amd", "ddcc.py")
+    dst = tmp_path / "ddcc_copy.py"
+    dst.write_text(open(src).read())
+    spec = importlib.util.spec_from_file_location("ddcc_copy", str(dst))
+    mod = importlib.util.module_from_spec(spec)
+    with pytest.raises(ImportError):
+        spec.loader.exec_module(mod)

@@ -1,0 +1,128 @@
+"""Parity of the 3D HIP path (D3Q15 phase sets, D3Q19 flow set) with the
+FP64 oracle, through the C ABI."""
+import numpy as np
+import pytest
+
+from paper_2311_10314_amd import workloads as W
+from tests.helpers import gpu_state_to_oracle, oracle_run, rel_linf
+
+pytestmark = pytest.mark.gpu
+
+
+def cases3d():
+    return [W.random_small(3, 2, (12, 10, 70), seed=31),
+            W.random_small(3, 3, (9, 13, 20), seed=32),
+            W.random_small(3, 2, (21, 6, 7), seed=33)]
+
+
+def gpu_run(wl, steps, precision="fp64", tile=None):
+    from paper_2311_10314_amd.ddcc import Sim
+    sim = Sim.from_workload(wl, precision)
+    if tile:
+        sim.set_tile(0, tile)
+    m0 = sim.mass()
+    sim.step(steps)
+    C, u, P = sim.read_moments()
+    return dict(C=C, u=u, P=P, mass0=m0, mass=sim.mass(), sim=sim)
+
+
+def _err(g, o):
+    return dict(C=max(rel_linf(g["C"][i], o["C"][i])
+                      for i in range(len(o["C"]))),
+                u=rel_linf(g["u"], o["u"]), P=rel_linf(g["P"], o["P"]))
+
+
+@pytest.mark.parametrize("k", range(3))
+def test_init_3d_fp64(k):
+    wl = cases3d()[k]
+    print("case", wl.name, wl.shape, flush=True)
+    e = _err(gpu_run(wl, 0), oracle_run(wl, 0))
+    print("init", e, flush=True)
+    assert e["C"] < 1e-13 and e["u"] < 1e-12 and e["P"] < 1e-10
+
+
+@pytest.mark.parametrize("k", range(3))
+def test_one_step_3d_fp64(k):
+    wl = cases3d()[k]
+    print("case", wl.name, wl.shape, flush=True)
+    o = oracle_run(wl, 1)
+    g = gpu_run(wl, 1)
+    st = gpu_state_to_oracle(wl, g["sim"])
+    ef = np.abs(st.f - o["state"].f).max() / np.abs(o["state"].f).max()
+    eg = np.abs(st.g - o["state"].g).max() / np.abs(o["state"].g).max()
+    e = _err(g, o)
+    print("one step f %.2e g %.2e" % (ef, eg), e, flush=True)
+    assert ef < 1e-13 and eg < 1e-13 and max(e.values()) < 1e-10
+
+
+@pytest.mark.parametrize("k", range(3))
+def test_short_run_3d_fp64(k):
+    wl = cases3d()[k]
+    print("case", wl.name, wl.shape, flush=True)
+    o = oracle_run(wl, 30)
+    g = gpu_run(wl, 30)
+    e = _err(g, o)
+    print("30 steps", e, flush=True)
+    assert max(e.values()) < 1e-10
+    drift = np.abs(g["mass"] - g["mass0"]) / np.abs(g["mass0"])
+    assert drift.max() < 1e-12
+
+
+def test_tile_invariance_3d():
+    wl = cases3d()[0]
+    a = gpu_run(wl, 10, tile=2)
+    b = gpu_run(wl, 10, tile=4)
+    assert np.array_equal(a["C"], b["C"]) and np.array_equal(a["u"], b["u"])
+
+
+@pytest.mark.parametrize("k", range(3))
+def test_short_run_3d_fp32(k):
+    wl = cases3d()[k]
+    o = oracle_run(wl, 30)
+    g = gpu_run(wl, 30, "fp32")
+    e = _err(g, o)
+    print("fp32 30 steps", e, flush=True)
+    assert e["C"] < 1e-5 and e["u"] < 1e-4
+    drift = np.abs(g["mass"] - g["mass0"]) / np.abs(g["mass0"])
+    assert drift.max() < 1e-6
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 1e-4)])
+def test_sphere_droplet_32(precision, tol):
+    """32^3 version of the sphere / impacting-droplet case (sizes scaled by
+    1/8), 40 steps against the oracle."""
+    wl = W.droplet_impact_sphere_3d(n=32)
+    o = oracle_run(wl, 40)
+    g = gpu_run(wl, 40, precision)
+    e = _err(g, o)
+    fl = wl.psi >= 1e-3
+    eP = rel_linf(g["P"][fl], o["P"][fl])
+    print("sphere32 %s" % precision, e, "P(psi>=1e-3) %.2e" % eP, flush=True)
+    assert e["C"] < tol and e["u"] < tol and eP < 10 * tol
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 2e-5)])
+def test_sphere_droplet_64_one_step(precision, tol):
+    """64^3 sphere case: GPU state after 50 steps, advanced one step by the
+    oracle, matches the GPU's next step at every node."""
+    import oracle
+    from paper_2311_10314_amd.ddcc import Sim
+    wl = W.droplet_impact_sphere_3d(n=64)
+    sim = Sim.from_workload(wl, precision)
+    sim.step(50)
+    st = gpu_state_to_oracle(wl, sim)
+    prm, geo, _ = oracle.from_workload(wl)
+    st1 = oracle.step(prm, geo, st)
+    Co, uo, Po = oracle.moments(prm, geo, st1)
+    sim.step(1)
+    C, u, P = sim.read_moments()
+    g1 = gpu_state_to_oracle(wl, sim)
+    eC = max(rel_linf(C[i], Co[i]) for i in range(2))
+    eu = rel_linf(u, uo)
+    fl = wl.psi >= 1e-3
+    eP = rel_linf(P[fl], Po[fl])
+    ef = np.abs(g1.f - st1.f).max() / np.abs(st1.f).max()
+    eg = np.abs(g1.g - st1.g).max() / np.abs(st1.g).max()
+    print("sphere64 %s one step: C %.2e u %.2e P %.2e f %.2e g %.2e" % (
+        precision, eC, eu, eP, ef, eg), flush=True)
+    assert max(eC, eu, ef, eg) < tol and eP < 100 * tol
