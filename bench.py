@@ -73,10 +73,47 @@ def make_workload(n):
     return W.porous_bands_2d(n=n)
 
 
-def time_gpu(wl, precision, steps, warmup, torch):
+def sphere_leg(n, steps, warmup, torch, precisions=("fp32", "fp64")):
+    """3D leg: the sphere / impacting-droplet box (D3Q15 phase sets, D3Q19
+    flow set, N = 2) at n^3."""
+    from paper_2311_10314_amd import workloads as W
+    wl = W.droplet_impact_sphere_3d(n=n)
+    out = {}
+    for prec in precisions:
+        esz = 4 if prec == "fp32" else 8
+        sim, ms, drift = time_gpu(wl, prec, steps, warmup, torch)
+        sim.close()
+        bpn = algorithmic_bytes_per_node(2, 3, 15, 19, esz)
+        achieved = bpn * wl.nodes / (ms * 1e-3) / 1e9
+        out[prec] = {"value": wl.nodes / (ms * 1e-3) / 1e6,
+                     "unit": "MLUPS", "ms_per_step": ms, "mass_drift": drift,
+                     "bytes_per_node": bpn, "achieved_GBs": achieved,
+                     "frac": achieved / HBM_PEAK_GBS, "steps": steps}
+        print("  sphere3d %d^3 %s: %.4f ms/step, %.0f MLUPS, %.0f GB/s" % (
+            n, prec, ms, out[prec]["value"], achieved), file=sys.stderr,
+            flush=True)
+    return out
+
+
+def copy_calibration(torch, mib=1024):
+    """A plain device copy of known size, for scaling the HBM byte counters
+    (FETCH_SIZE / WRITE_SIZE) read on the step kernel."""
+    a = torch.empty(mib * 1024 * 1024 // 4, dtype=torch.float32,
+                    device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print("copy calibration: 3 copies of %d MiB" % mib, file=sys.stderr,
+          flush=True)
+
+
+def time_gpu(wl, precision, steps, warmup, torch, tile=0):
     from paper_2311_10314_amd.ddcc import Sim
     stream = torch.cuda.Stream()
     sim = Sim.from_workload(wl, precision, stream=stream.cuda_stream)
+    if tile:
+        sim.set_tile(0, tile)
     m0 = sim.mass()
     sim.step(warmup)
     sim.sync()
@@ -150,6 +187,12 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=8)
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--tile", type=int, default=0)
+    ap.add_argument("--sphere", type=int, default=0,
+                    help="also time the 3D sphere box at this n (0: skip)")
+    ap.add_argument("--sphere-steps", type=int, default=200)
+    ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--precision", default="both",
+                    choices=["both", "fp32", "fp64"])
     a = ap.parse_args()
     if a.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU "
@@ -163,11 +206,17 @@ def main():
     wl = make_workload(a.n)
     N = wl.nphase
     res = {}
-    for prec, esz in (("fp32", 4), ("fp64", 8)):
+    if a.copy_calibration:
+        copy_calibration(torch)
+    precs = (("fp32", 4), ("fp64", 8))
+    if a.precision != "both":
+        precs = tuple(x for x in precs if x[0] == a.precision)
+    for prec, esz in precs:
         print("timing %s: %d warmup + %d steps on %s" % (prec, a.warmup,
                                                          a.steps, wl.shape),
               file=sys.stderr, flush=True)
-        sim, ms, drift = time_gpu(wl, prec, a.steps, a.warmup, torch)
+        sim, ms, drift = time_gpu(wl, prec, a.steps, a.warmup, torch,
+                                  a.tile)
         sim.close()
         bpn = algorithmic_bytes_per_node(N, 2, 9, 9, esz)
         per_launch = bpn * wl.nodes
@@ -188,6 +237,12 @@ def main():
         print("  %s: %.4f ms/step, %.0f MLUPS, %.0f GB/s" % (
             prec, ms, res[prec]["value"], achieved), file=sys.stderr,
             flush=True)
+    sphere = None
+    if a.sphere:
+        print("timing the 3D sphere box at %d^3" % a.sphere, file=sys.stderr,
+              flush=True)
+        sphere = sphere_leg(a.sphere, a.sphere_steps, 10, torch,
+                            tuple(p for p, _ in precs))
     err = None
     cpu = None
     if not a.skip_cpu:
@@ -195,6 +250,9 @@ def main():
               flush=True)
         err = error_vs_oracle(wl, 10)
         cpu = cpu_baseline(wl, a.cpu_steps)
+    if "fp32" not in res:
+        print(json.dumps({"fp64": res["fp64"], "sphere3d": sphere}))
+        return 0
     f32 = res["fp32"]
     line = {
         "metric": METRIC, "value": f32["value"], "unit": "MLUPS",
@@ -211,7 +269,8 @@ def main():
         "roofline": f32["roofline"],
         "cpu_baseline": cpu,
         "error_vs_oracle": err,
-        "fp64": res["fp64"],
+        "fp64": res.get("fp64"),
+        "sphere3d": sphere,
     }
     print(json.dumps(line), flush=True)
     return 0

@@ -11,6 +11,7 @@
 #include "../../include/ddcc.h"
 #include "coef.hpp"
 #include "kernels.hpp"
+#include "lattice.hpp"
 
 using namespace ddcc;
 
@@ -209,6 +210,42 @@ int validate(const ddcc_params* p, std::string& msg) {
   return DDCC_OK;
 }
 
+template <class L>
+void fourth_order_q_for(double d0, double q4[3][3]) {
+  double w[19];
+  lattice_weights(L::ID, d0, w);
+  const double cs2 = d0;
+  for (int j = 0; j < 3; ++j)
+    for (int g = 0; g < 3; ++g) q4[j][g] = 0;
+  for (int k = 0; k < L::Q; ++k) {
+    const int j = g4_index<L>(k);
+    if (j < 0) continue;
+    for (int g = 0; g < L::D; ++g) {
+      double s = 0;
+      for (int p = 0; p < L::Q; ++p) {
+        const int cg = g == 0 ? L::c[p].x : (g == 1 ? L::c[p].y : L::c[p].z);
+        s += w[p] * row_value<L>(k, p, cs2) * (cg * cg - cs2);
+      }
+      s /= cs2 - cs2 * cs2;
+      q4[j][g] = std::fabs(s) < 1e-14 ? 0.0 : s;
+    }
+  }
+}
+
+// q4 of coef.hpp for the flow lattice.
+void fourth_order_q(int lat, double d0, double q4[3][3]) {
+  switch (lat) {
+    case DDCC_D3Q15:
+      fourth_order_q_for<D3Q15>(d0, q4);
+      break;
+    case DDCC_D3Q19:
+      fourth_order_q_for<D3Q19>(d0, q4);
+      break;
+    default:
+      fourth_order_q_for<D2Q9>(d0, q4);
+  }
+}
+
 template <class R>
 void fill_coef(const ddcc_params& p, long long n, Coef<R>& k) {
   std::memset(&k, 0, sizeof(k));
@@ -264,6 +301,10 @@ void fill_coef(const ddcc_params& p, long long n, Coef<R>& k) {
     k.accel[a] = R(p.accel[a]);
     k.force[a] = R(p.force[a]);
   }
+  double q4[3][3];
+  fourth_order_q(p.lattice_g, p.d0, q4);
+  for (int j = 0; j < 3; ++j)
+    for (int g = 0; g < 3; ++g) k.q4[j][g] = R(q4[j][g]);
 }
 
 template <class S>

@@ -32,6 +32,11 @@ struct Coef {
   R halfK;                // K / (2 c^2)                (eq. 19)
   R KH;                   // K * (1 - 2 d0) in 2D, K (3 - 7 d0)/2 in 3D
   R one_m3cs2;            // c^2 - 3 c_s^2              (eq. 3.12)
+  // Fourth-order Hermite moments of the second-order expansion used in the
+  // flow equilibrium and source (eqs. 3.10, 3.11): for the j-th fourth-order
+  // row k of the flow set, q4[j][g] = sum_p w_p H_k(c_p) (c_pg^2 - c_s^2) /
+  // (c^2 c_s^2 - c_s^4). Zero on D2Q9.
+  R q4[3][3];
   R accel[3];             // body acceleration: force psi rho a
   R force[3];             // body force density: force psi G
 };

@@ -349,6 +349,118 @@ __host__ __device__ inline void from_hermite(const R* m, R* out, R cs2) {
   from_hermite_impl<L>(m, out, cs2, std::make_integer_sequence<int, L::Q>{});
 }
 
+template <class L, class R, int... k>
+__host__ __device__ inline void raw_impl(const R* d, R* r,
+                                         std::integer_sequence<int, k...>) {
+  ((r[k] = raw_row<L, k>(d, std::make_integer_sequence<int, L::Q>{})), ...);
+}
+
+// r = R d: raw monomial moments (integer coefficients, sparse adds)
+template <class L, class R>
+__host__ __device__ inline void raw_moments(const R* d, R* r) {
+  raw_impl<L>(d, r, std::make_integer_sequence<int, L::Q>{});
+}
+
+template <class L, class R, int... k>
+__host__ __device__ inline void r2h_impl(const R* r, R* m, R cs2,
+                                         std::integer_sequence<int, k...>) {
+  const R cs4 = cs2 * cs2, cs6 = cs4 * cs2;
+  ((m[k] = herm_row<L, k>(r, cs2, cs4, cs6,
+                          std::make_integer_sequence<int, k>{})), ...);
+}
+
+// m = A(cs2) r: Hermite moments from raw moments
+template <class L, class R>
+__host__ __device__ inline void raw_to_hermite(const R* r, R* m, R cs2) {
+  r2h_impl<L>(r, m, cs2, std::make_integer_sequence<int, L::Q>{});
+}
+
+// Order of a Hermite row (number of c factors, counting c^2 - cs2 as two).
+template <class L>
+__host__ __device__ constexpr int row_order(int k) {
+  int o = 0;
+  for (int a = 0; a < 3; ++a) o += L::rows[k].t[0].f[a];
+  return o;
+}
+
+// Value of Hermite row k at c = 0 divided by (-cs2)^(order/2): the product
+// of its (c_a^2 - cs2) factors is (-cs2)^m, summed over the row's terms,
+// and rows with a bare c_a factor vanish there. Returns the integer
+// multiplicity (0 for rows that vanish at rest).
+template <class L>
+__host__ __device__ constexpr int rest_multiplicity(int k) {
+  int mult = 0;
+  for (int t = 0; t < L::rows[k].nterm; ++t) {
+    bool zero = false;
+    for (int a = 0; a < 3; ++a)
+      if (L::rows[k].t[t].f[a] == 1) zero = true;
+    if (!zero) ++mult;
+  }
+  return mult;
+}
+
+// Value of Hermite row k at c = 0, a polynomial in cs2.
+template <class L, int k, class R>
+__host__ __device__ inline R rest_value(R cs2) {
+  R v = R(0);
+#pragma unroll
+  for (int t = 0; t < L::rows[k].nterm; ++t) {
+    R prod = R(1);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const int f = L::rows[k].t[t].f[a];
+      if (f == 1) prod = R(0);
+      if (f == 2) prod *= -cs2;
+    }
+    v += prod;
+  }
+  return v;
+}
+
+// Hermite row k evaluated at velocity c (host-side, for derived constants).
+template <class L>
+inline double row_value(int k, int p, double cs2) {
+  const int cc[3] = {L::c[p].x, L::c[p].y, L::c[p].z};
+  double v = 0;
+  for (int t = 0; t < L::rows[k].nterm; ++t) {
+    double prod = 1;
+    for (int a = 0; a < 3; ++a) {
+      const int f = L::rows[k].t[t].f[a];
+      if (f == 1) prod *= cc[a];
+      if (f == 2) prod *= cc[a] * cc[a] - cs2;
+    }
+    v += prod;
+  }
+  return v;
+}
+
+// Index among the fourth-order rows (0, 1, 2) of row k, -1 otherwise.
+template <class L>
+__host__ __device__ constexpr int g4_index(int k) {
+  int j = -1;
+  for (int q = 0; q <= k; ++q)
+    if (L::rows[q].group == GR4) ++j;
+  return L::rows[k].group == GR4 ? j : -1;
+}
+
+// Component of a first-order row / diagonal second-order row, and the pair
+// index (xy, xz, yz) of an off-diagonal second-order row.
+template <class L>
+__host__ __device__ constexpr int row_comp(int k) {
+  for (int a = 0; a < 3; ++a)
+    if (L::rows[k].t[0].f[a] != 0) return a;
+  return -1;
+}
+
+template <class L>
+__host__ __device__ constexpr int row_pair(int k) {
+  // (x, y) -> 0, (x, z) -> 1, (y, z) -> 2
+  const int* f = L::rows[k].t[0].f;
+  if (f[0] && f[1]) return 0;
+  if (f[0] && f[2]) return 1;
+  return 2;
+}
+
 // Relaxation slot of Hermite row k.
 template <class L>
 __host__ __device__ constexpr int row_group(int k) {

@@ -31,6 +31,7 @@
 #include "coef.hpp"
 #include "common.hpp"
 #include "kernels.hpp"
+#include "collide.hpp"
 #include "lattice.hpp"
 
 namespace ddcc {
@@ -87,10 +88,10 @@ __device__ inline Patch<R> patch(const R (&a)[H][W], int x, int y) {
 // Pull: population p at (gx, gy) comes from (gx - c_px, gy - c_py).
 struct Nbr {
   int xm, xp, ym, yp, x, y, nx;
-  __device__ inline int src(int cx, int cy) const {
+  __device__ inline unsigned src(int cx, int cy) const {
     const int sx = cx == 1 ? xm : (cx == -1 ? xp : x);
     const int sy = cy == 1 ? ym : (cy == -1 ? yp : y);
-    return sy * nx + sx;
+    return unsigned(sy * nx + sx);
   }
 };
 
@@ -159,12 +160,12 @@ struct Step2D {
                                       const Bufs<S>& b, int x0, int y0, int lx,
                                       int ly, D* psiC_out) {
     const int gx = wrap(x0 + lx - 2, k.nx), gy = wrap(y0 + ly - 2, k.ny);
-    const long long idx = (long long)gy * k.nx + gx;
-    const D psi = ld<S, D>(b.psi + idx);
+    const unsigned idx = unsigned(gy * k.nx + gx);
+    const D psi = ld<S, D>(&b.psi[idx]);
     D rho = D(0);
     if constexpr (MODE == MODE_INIT) {
 #pragma unroll
-      for (int i = 0; i < N; ++i) psiC_out[i] = psi * b.inC[i * k.n + idx];
+      for (int i = 0; i < N; ++i) psiC_out[i] = psi * (b.inC + (long long)(i) * k.n)[idx];
     } else {
       const Nbr nb = make_nbr(gx, gy, k.nx, k.ny);
 #pragma unroll
@@ -172,11 +173,13 @@ struct Step2D {
         // phi C_i = sum_p f^i_p (Section 3); the rest population does not
         // move and lives in the float64 plane
         const S* f = b.fA + (long long)i * Q * k.n;
-        D s = b.f0A[i * k.n + idx];
+        // moving populations summed in the storage precision, the float64
+        // rest population added last
+        R mv = R(0);
 #pragma unroll
         for (int p = 1; p < Q; ++p)
-          s += ld<S, D>(f + p * k.n + nb.src(D2Q9::c[p].x, D2Q9::c[p].y));
-        psiC_out[i] = s;
+          mv += ld<S, R>(&(f + (long long)(p) * k.n)[nb.src(D2Q9::c[p].x, D2Q9::c[p].y)]);
+        psiC_out[i] = (b.f0A + (long long)(i) * k.n)[idx] + D(mv);
       }
     }
     // C_i = phi C_i / sum_j phi C_j: equal to phi C_i / phi while the
@@ -201,7 +204,7 @@ struct Step2D {
                                       int my, D* psimu_out) {
     const int lx = mx + 1, ly = my + 1;
     const int gx = wrap(x0 + mx - 1, k.nx), gy = wrap(y0 + my - 1, k.ny);
-    const long long idx = (long long)gy * k.nx + gx;
+    const unsigned idx = unsigned(gy * k.nx + gx);
     const Patch<D> ps = patch(sm.psi, lx, ly);
     const D psi = ps.v[1][1];
     const D psih = psi > k.psi_min ? psi : k.psi_min;
@@ -217,7 +220,7 @@ struct Step2D {
     // cos theta_jq from the N-1 stored cos theta_iN (eq. 2.9)
     D ct[N];
 #pragma unroll
-    for (int i = 0; i < N - 1; ++i) ct[i] = ld<S, D>(b.ct + i * k.n + idx);
+    for (int i = 0; i < N - 1; ++i) ct[i] = ld<S, D>(&(b.ct + (long long)(i) * k.n)[idx]);
     ct[N - 1] = D(0);
     D W[N];  // sum_{q != j} cos theta_jq C_j C_q
 #pragma unroll
@@ -247,7 +250,7 @@ struct Step2D {
       psimu_out[i] = pm;
       sm.mu[i][my][mx] = pm / psih;
     }
-    if constexpr (MODE != MODE_INIT) sm.T[my][mx] = ld<S, R>(b.TA + idx);
+    if constexpr (MODE != MODE_INIT) sm.T[my][mx] = ld<S, R>(&b.TA[idx]);
   }
 
   __device__ static void run(const Coef<D>& kd, const Coef<R>& k,
@@ -279,7 +282,7 @@ struct Step2D {
     const int gx = x0 + tx, gy = y0 + ty;
     if (gx >= k.nx || gy >= k.ny) return;
     const long long n = k.n;
-    const long long idx = (long long)gy * k.nx + gx;
+    const unsigned idx = unsigned(gy * k.nx + gx);
     const int lx = tx + 2, ly = ty + 2, mx = tx + 1, my = ty + 1;
 
     // ---- gradients from LDS -------------------------------------------
@@ -333,12 +336,12 @@ struct Step2D {
     const Nbr nb = make_nbr(gx, gy, k.nx, k.ny);
     if constexpr (MODE == MODE_INIT) {
       u[0] = b.inU ? R(b.inU[idx]) : R(0);
-      u[1] = b.inU ? R(b.inU[n + idx]) : R(0);
+      u[1] = b.inU ? R((b.inU + n)[idx]) : R(0);
     } else {
       R j[2] = {R(0), R(0)};
 #pragma unroll
       for (int p = 0; p < Q; ++p) {
-        gp[p] = ld<S, R>(b.gA + p * n + nb.src(D2Q9::c[p].x, D2Q9::c[p].y));
+        gp[p] = ld<S, R>(&(b.gA + (long long)(p) * n)[nb.src(D2Q9::c[p].x, D2Q9::c[p].y)]);
         if (p > 0) sum_gm += gp[p];
         if (D2Q9::c[p].x) j[0] += R(D2Q9::c[p].x) * gp[p];
         if (D2Q9::c[p].y) j[1] += R(D2Q9::c[p].y) * gp[p];
@@ -346,7 +349,7 @@ struct Step2D {
       // force (eq. 3.13): -div T^{n-1} + sum_i phi mu_i grad C_i
       //                   + P^{n-1} grad psi + psi (rho a + G)
       const Patch<R> tp = patch(sm.T, mx, my);
-      const R Pprev = ld<S, R>(b.hist + (2 * N + 3) * n + idx);
+      const R Pprev = ld<S, R>(&(b.hist + (long long)((2 * N + 3)) * n)[idx]);
       R Fp[2];
       Fp[0] = grad_y(tp) + Pprev * gpsi[0] + psirho * k.accel[0] +
               psi * k.force[0];
@@ -375,7 +378,7 @@ struct Step2D {
     if constexpr (MODE != MODE_INIT) {
 #pragma unroll
       for (int q = 0; q < 3; ++q)
-        dtY[q] = Y[q] - ld<S, R>(b.hist + (2 * N + q) * n + idx);
+        dtY[q] = Y[q] - ld<S, R>(&(b.hist + (long long)((2 * N + q)) * n)[idx]);
     }
 
     // local flow rates from nu (eq. 16)
@@ -403,16 +406,15 @@ struct Step2D {
 
     if constexpr (MODE == MODE_MOMENTS) {
 #pragma unroll
-      for (int i = 0; i < N; ++i) b.outC[i * n + idx] = double(C[i]);
+      for (int i = 0; i < N; ++i) (b.outC + (long long)(i) * n)[idx] = double(C[i]);
       b.outU[idx] = double(u[0]);
-      b.outU[n + idx] = double(u[1]);
+      (b.outU + n)[idx] = double(u[1]);
       b.outP[idx] = double(P);
       return;
     }
 
     // ---- flow set: equilibrium (eqs. 3.8, 3.11), source (3.10, 3.12) ---
-    {
-      R d[Q], G[Q];
+    if constexpr (MODE == MODE_INIT) {
 #pragma unroll
       for (int p = 0; p < Q; ++p) {
         const int cx = D2Q9::c[p].x, cy = D2Q9::c[p].y;
@@ -422,55 +424,44 @@ struct Step2D {
         R geq = k.wg[p] * ((psiP + R(cx) * psirho * u[0] + R(cy) * psirho * u[1]) *
                                k.inv_cs2 + h2);
         if (p == 0) geq -= psiP * k.inv_cs2;  // stored as g_0 - rho0
-        if constexpr (MODE == MODE_INIT) {
-          d[p] = geq;
-        } else {
-          d[p] = gp[p] - geq;
-        }
+        // the buffers hold pre-streaming values: place g_p(x) where the
+        // next pull reads it, at x - c_p
+        (b.gB + (long long)(p) * n)[nb.src(cx, cy)] = S(geq);
       }
-      if constexpr (MODE == MODE_INIT) {
-        // the buffers hold pre-streaming values: place g_p(x) where the next
-        // pull reads it, at x - c_p
+    } else {
+      const R ub = u[0] * gprho[0] + u[1] * gprho[1];
+      // M^{2G} (eq. 3.12), scalar u.grad(phi rho) on the diagonal
+      const R M[3] = {dtY[0] + R(2) * k.cs2 * u[0] * gprho[0] + k.one_m3cs2 * ub,
+                      dtY[1] + k.cs2 * (u[0] * gprho[1] + gprho[0] * u[1]),
+                      dtY[2] + R(2) * k.cs2 * u[1] * gprho[1] + k.one_m3cs2 * ub};
+      const R a0 = psi * (u[0] * grho[0] + u[1] * grho[1]);
+      const R J[2] = {psirho * u[0], psirho * u[1]};
+      R del[Q];
+      collide_flow<D2Q9>(gp, J, A, psiP, M, a0, F, s21, s22, k.sg, k.q4,
+                         k.cs2, k.inv_cs2, del);
 #pragma unroll
-        for (int p = 0; p < Q; ++p)
-          b.gB[p * n + nb.src(D2Q9::c[p].x, D2Q9::c[p].y)] = S(d[p]);
-      } else {
-        const R ub = u[0] * gprho[0] + u[1] * gprho[1];
-        const R M[3] = {dtY[0] + R(2) * k.cs2 * u[0] * gprho[0] + k.one_m3cs2 * ub,
-                        dtY[1] + k.cs2 * (u[0] * gprho[1] + gprho[0] * u[1]),
-                        dtY[2] + R(2) * k.cs2 * u[1] * gprho[1] + k.one_m3cs2 * ub};
-        const R a0 = psi * (u[0] * grho[0] + u[1] * grho[1]);
-#pragma unroll
-        for (int p = 0; p < Q; ++p) {
-          const int cx = D2Q9::c[p].x, cy = D2Q9::c[p].y;
-          const R h2 = (M[0] * (R(cx * cx) - k.cs2) + M[2] * (R(cy * cy) - k.cs2)) *
-                           k.h2diag +
-                       M[1] * R(cx * cy) * k.h2off;
-          G[p] = k.wg[p] * (a0 + (R(cx) * F[0] + R(cy) * F[1]) * k.inv_cs2 + h2);
-        }
-        R m[Q], mg[Q], ms[Q], del[Q];
-        to_hermite<D2Q9>(d, m, k.cs2);
-        to_hermite<D2Q9>(G, mg, k.cs2);
-#pragma unroll
-        for (int q = 0; q < Q; ++q) {
-          const int grp = D2Q9::rows[q].group;
-          const R s = grp == GR21 ? s21 : (grp == GR22 ? s22 : k.sg[grp]);
-          ms[q] = s * m[q] - (R(1) - R(0.5) * s) * mg[q];
-        }
-        from_hermite<D2Q9>(ms, del, k.cs2);
-#pragma unroll
-        for (int p = 0; p < Q; ++p) b.gB[p * n + idx] = S(gp[p] - del[p]);
-      }
+      for (int p = 0; p < Q; ++p) (b.gB + (long long)(p) * n)[idx] = S(gp[p] - del[p]);
     }
 
     // ---- phase sets: equilibrium (3.5), source (3.6, 3.7), collision ---
 #pragma unroll
     for (int i = 0; i < N; ++i) {
       const R X[2] = {R(psiC[i]) * u[0], R(psiC[i]) * u[1]};
-      R V[2] = {R(0), R(0)};
-      if constexpr (MODE != MODE_INIT) {
+      const R em = k.eta[i] * psimu[i];
+      const S* fsrc = b.fA + (long long)i * Q * n;
+      S* fdst = b.fB + (long long)i * Q * n;
+      if constexpr (MODE == MODE_INIT) {
+        // f^eq_0 = (w_0 - 1) eta phi mu + phi C (float64 rest plane)
+        (b.f0B + (long long)(i) * n)[idx] = (kd.wf[0] - D(1)) * kd.eta[i] * psimu_d[i] + psiC[i];
+#pragma unroll
+        for (int p = 1; p < Q; ++p) {
+          const int cx = D2Q9::c[p].x, cy = D2Q9::c[p].y;
+          const R feq = k.wf[p] * (em + (R(cx) * X[0] + R(cy) * X[1]) * k.inv_cs2);
+          (fdst + (long long)(p) * n)[nb.src(cx, cy)] = S(feq);
+        }
+      } else {
         // S_i = psi [(C_i sum_{j!=i} C_j - 1) grad mu_i
-        //            - C_i sum_{j != i} C_j grad mu_j]
+        //            - C_i sum_{j != i} C_j grad mu_j]     (eq. 3.7)
         R Sx = (C[i] * Cs[i] - R(1)) * gmu[i][0];
         R Sy = (C[i] * Cs[i] - R(1)) * gmu[i][1];
 #pragma unroll
@@ -481,63 +472,27 @@ struct Step2D {
           }
         Sx *= psi;
         Sy *= psi;
-        const R dX0 = X[0] - ld<S, R>(b.hist + (2 * i) * n + idx);
-        const R dX1 = X[1] - ld<S, R>(b.hist + (2 * i + 1) * n + idx);
-        V[0] = dX0 + k.cs2 * k.eta[i] * (mu[i] * gpsi[0] - Sx);
-        V[1] = dX1 + k.cs2 * k.eta[i] * (mu[i] * gpsi[1] - Sy);
-      }
-      const R em = k.eta[i] * psimu[i];
-      R d[Q];
-      const S* fsrc = b.fA + (long long)i * Q * n;
-      S* fdst = b.fB + (long long)i * Q * n;
-      R fp[Q];
-      // rest population in float64: f^eq_0 = (w_0 - 1) eta phi mu + phi C
-      const D feq0 = (kd.wf[0] - D(1)) * kd.eta[i] * psimu_d[i] + psiC[i];
-      D f0 = D(0);
-      if constexpr (MODE != MODE_INIT) f0 = b.f0A[i * n + idx];
-      d[0] = R(f0 - feq0);
-#pragma unroll
-      for (int p = 1; p < Q; ++p) {
-        const int cx = D2Q9::c[p].x, cy = D2Q9::c[p].y;
-        const R feq = k.wf[p] * (em + (R(cx) * X[0] + R(cy) * X[1]) * k.inv_cs2);
-        if constexpr (MODE == MODE_INIT) {
-          d[p] = feq;
-        } else {
-          fp[p] = ld<S, R>(fsrc + p * n + nb.src(cx, cy));
-          d[p] = fp[p] - feq;
-        }
-      }
-      if constexpr (MODE == MODE_INIT) {
-        b.f0B[i * n + idx] = feq0;
+        const R dX0 = X[0] - ld<S, R>(&(b.hist + (long long)((2 * i)) * n)[idx]);
+        const R dX1 = X[1] - ld<S, R>(&(b.hist + (long long)((2 * i + 1)) * n)[idx]);
+        const R V[2] = {dX0 + k.cs2 * k.eta[i] * (mu[i] * gpsi[0] - Sx),
+                        dX1 + k.cs2 * k.eta[i] * (mu[i] * gpsi[1] - Sy)};
+        R fp[Q];
+        fp[0] = R(0);
 #pragma unroll
         for (int p = 1; p < Q; ++p)
-          fdst[p * n + nb.src(D2Q9::c[p].x, D2Q9::c[p].y)] = S(d[p]);
-      } else {
-        R Fs[Q];
+          fp[p] = ld<S, R>(&(fsrc + (long long)(p) * n)[nb.src(D2Q9::c[p].x, D2Q9::c[p].y)]);
+        R del[Q];
+        collide_phase<D2Q9>(fp, em, X, V, k.sf, k.cs2, del);
+        (b.f0B + (long long)(i) * n)[idx] = (b.f0A + (long long)(i) * n)[idx] - D(del[0]);
 #pragma unroll
-        for (int p = 0; p < Q; ++p) {
-          const int cx = D2Q9::c[p].x, cy = D2Q9::c[p].y;
-          Fs[p] = k.wf[p] * (R(cx) * V[0] + R(cy) * V[1]) * k.inv_cs2;
-        }
-        R m[Q], mf[Q], ms[Q], del[Q];
-        to_hermite<D2Q9>(d, m, k.cs2);
-        to_hermite<D2Q9>(Fs, mf, k.cs2);
-#pragma unroll
-        for (int q = 0; q < Q; ++q) {
-          const R s = k.sf[D2Q9::rows[q].group];
-          ms[q] = s * m[q] - (R(1) - R(0.5) * s) * mf[q];
-        }
-        from_hermite<D2Q9>(ms, del, k.cs2);
-        b.f0B[i * n + idx] = f0 - D(del[0]);
-#pragma unroll
-        for (int p = 1; p < Q; ++p) fdst[p * n + idx] = S(fp[p] - del[p]);
+        for (int p = 1; p < Q; ++p) (fdst + (long long)(p) * n)[idx] = S(fp[p] - del[p]);
       }
-      b.hist[(2 * i) * n + idx] = S(X[0]);
-      b.hist[(2 * i + 1) * n + idx] = S(X[1]);
+      (b.hist + (long long)((2 * i)) * n)[idx] = S(X[0]);
+      (b.hist + (long long)((2 * i + 1)) * n)[idx] = S(X[1]);
     }
 #pragma unroll
-    for (int q = 0; q < 3; ++q) b.hist[(2 * N + q) * n + idx] = S(Y[q]);
-    b.hist[(2 * N + 3) * n + idx] = S(P);
+    for (int q = 0; q < 3; ++q) (b.hist + (long long)((2 * N + q)) * n)[idx] = S(Y[q]);
+    (b.hist + (long long)((2 * N + 3)) * n)[idx] = S(P);
     b.TB[idx] = S(Tn);
   }
 };

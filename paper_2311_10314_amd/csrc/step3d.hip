@@ -33,13 +33,6 @@ namespace {
 
 constexpr int TX = 64;
 
-// 3x3x3 neighbourhood [dz+1][dy+1][dx+1]; the 8 corners are not used by the
-// D3Q19-weight stencil.
-template <class T>
-struct Patch3 {
-  T v[3][3][3];
-};
-
 // Fixed isotropic stencil: D3Q19 weights at d0 = 1/3 (1/18 faces, 1/36
 // edges) divided by c_s^2 = 1/3, i.e. 1/6 on faces and 1/12 on edges.
 template <int q>
@@ -50,46 +43,45 @@ constexpr double stencil_w() {
              : 1.0 / 12.0;
 }
 
-template <class T, int a, int q>
-__device__ inline void grad_term(T& s, const Patch3<T>& p) {
+// Accessor forms: at(dx, dy, dz) returns the field at the offset; the sum
+// runs over the 18 D3Q19 neighbours with compile-time offsets.
+template <int a, class T, class F, int q>
+__device__ inline void agrad_term(T& s, F& at) {
   constexpr int cx = D3Q19::c[q].x, cy = D3Q19::c[q].y, cz = D3Q19::c[q].z;
   constexpr int comp = a == 0 ? cx : (a == 1 ? cy : cz);
-  if constexpr (comp != 0)
-    s += T(comp * stencil_w<q>()) * p.v[cz + 1][cy + 1][cx + 1];
+  if constexpr (comp != 0) s += T(comp * stencil_w<q>()) * at(cx, cy, cz);
 }
 
-template <class T, int a, int... q>
-__device__ inline T grad_impl(const Patch3<T>& p,
-                              std::integer_sequence<int, q...>) {
+template <int a, class T, class F, int... q>
+__device__ inline T agrad_impl(F& at, std::integer_sequence<int, q...>) {
   T s = T(0);
-  (grad_term<T, a, q + 1>(s, p), ...);
+  (agrad_term<a, T, F, q + 1>(s, at), ...);
   return s;
 }
 
-template <int a, class T>
-__device__ inline T grad3(const Patch3<T>& p) {
-  return grad_impl<T, a>(p, std::make_integer_sequence<int, 18>{});
+template <int a, class T, class F>
+__device__ inline T agrad(F&& at) {
+  return agrad_impl<a, T>(at, std::make_integer_sequence<int, 18>{});
 }
 
-template <class T, int q>
-__device__ inline void lap_term(T& s, const Patch3<T>& ps, const Patch3<T>& c) {
+template <class T, class FP, class FC, int q>
+__device__ inline void alap_term(T& s, FP& ps, FC& c, T pc, T cc) {
   constexpr int cx = D3Q19::c[q].x, cy = D3Q19::c[q].y, cz = D3Q19::c[q].z;
-  s += T(stencil_w<q>()) * (ps.v[cz + 1][cy + 1][cx + 1] + ps.v[1][1][1]) *
-       (c.v[cz + 1][cy + 1][cx + 1] - c.v[1][1][1]);
+  s += T(stencil_w<q>()) * (ps(cx, cy, cz) + pc) * (c(cx, cy, cz) - cc);
 }
 
-template <class T, int... q>
-__device__ inline T lap_impl(const Patch3<T>& ps, const Patch3<T>& c,
-                             std::integer_sequence<int, q...>) {
+template <class T, class FP, class FC, int... q>
+__device__ inline T alap_impl(FP& ps, FC& c, std::integer_sequence<int, q...>) {
+  const T pc = ps(0, 0, 0), cc = c(0, 0, 0);
   T s = T(0);
-  (lap_term<T, q + 1>(s, ps, c), ...);
+  (alap_term<T, FP, FC, q + 1>(s, ps, c, pc, cc), ...);
   return s;
 }
 
-// div(psi grad C) in conservative two-point-flux form (eq. 2.14 term).
-template <class T>
-__device__ inline T div_psi_grad3(const Patch3<T>& ps, const Patch3<T>& c) {
-  return lap_impl(ps, c, std::make_integer_sequence<int, 18>{});
+// div(psi grad C) in conservative two-point-flux form, accessor version.
+template <class T, class FP, class FC>
+__device__ inline T adiv_psi_grad(FP&& ps, FC&& c) {
+  return alap_impl<T>(ps, c, std::make_integer_sequence<int, 18>{});
 }
 
 struct Nbr3 {
@@ -177,42 +169,6 @@ struct Step3D {
     sm.psi[s4][ly][lx] = psiS;
   }
 
-  __device__ static inline Patch3<D> cpatch(const Smem& sm, int i, int z,
-                                            int lx, int ly) {
-    Patch3<D> p;
-#pragma unroll
-    for (int dz = -1; dz <= 1; ++dz) {
-      const int s4 = slot(z + dz, NCP);
-#pragma unroll
-      for (int dy = -1; dy <= 1; ++dy)
-#pragma unroll
-        for (int dx = -1; dx <= 1; ++dx)
-          p.v[dz + 1][dy + 1][dx + 1] =
-              (dx != 0 && dy != 0 && dz != 0)
-                  ? D(0)
-                  : sm.C[s4][i][ly + dy][lx + dx];
-    }
-    return p;
-  }
-
-  __device__ static inline Patch3<D> psipatch(const Smem& sm, int z, int lx,
-                                              int ly) {
-    Patch3<D> p;
-#pragma unroll
-    for (int dz = -1; dz <= 1; ++dz) {
-      const int s4 = slot(z + dz, NCP);
-#pragma unroll
-      for (int dy = -1; dy <= 1; ++dy)
-#pragma unroll
-        for (int dx = -1; dx <= 1; ++dx)
-          p.v[dz + 1][dy + 1][dx + 1] =
-              (dx != 0 && dy != 0 && dz != 0)
-                  ? D(0)
-                  : D(sm.psi[s4][ly + dy][lx + dx]);
-    }
-    return p;
-  }
-
   // mu plane z at mu-region coordinates (mx, my): phi mu_i (eq. 2.14)
   __device__ static inline void node2(Smem& sm, const Coef<D>& k,
                                       const Bufs<S>& b, int x0, int y0, int z,
@@ -221,17 +177,23 @@ struct Step3D {
     const int gx = wrap(x0 + mx - 1, k.nx), gy = wrap(y0 + my - 1, k.ny);
     const int gz = wrap(z, k.nz);
     const long long idx = ((long long)gz * k.ny + gy) * k.nx + gx;
-    const Patch3<D> ps = psipatch(sm, z, lx, ly);
-    const D psi = ps.v[1][1][1];
+    const int sl[3] = {slot(z - 1, NCP), slot(z, NCP), slot(z + 1, NCP)};
+    auto psi_at = [&](int dx, int dy, int dz) {
+      return D(sm.psi[sl[dz + 1]][ly + dy][lx + dx]);
+    };
+    const D psi = psi_at(0, 0, 0);
     const D psih = psi > k.psi_min ? psi : k.psi_min;
-    const D g0 = grad3<0>(ps), g1 = grad3<1>(ps), g2 = grad3<2>(ps);
+    const D g0 = agrad<0, D>(psi_at), g1 = agrad<1, D>(psi_at),
+            g2 = agrad<2, D>(psi_at);
     const D agp = sqrt(g0 * g0 + g1 * g1 + g2 * g2);
     D C[N], L[N];
 #pragma unroll
     for (int j = 0; j < N; ++j) {
-      const Patch3<D> cp = cpatch(sm, j, z, lx, ly);
-      C[j] = cp.v[1][1][1];
-      L[j] = div_psi_grad3(ps, cp);
+      auto c_at = [&](int dx, int dy, int dz) {
+        return sm.C[sl[dz + 1]][j][ly + dy][lx + dx];
+      };
+      C[j] = c_at(0, 0, 0);
+      L[j] = adiv_psi_grad<D>(psi_at, c_at);
     }
     D ct[N];
 #pragma unroll
@@ -270,42 +232,6 @@ struct Step3D {
     }
   }
 
-  __device__ static inline Patch3<D> mupatch(const Smem& sm, int i, int z,
-                                             int mx, int my) {
-    Patch3<D> p;
-#pragma unroll
-    for (int dz = -1; dz <= 1; ++dz) {
-      const int s3 = slot(z + dz, NMP);
-#pragma unroll
-      for (int dy = -1; dy <= 1; ++dy)
-#pragma unroll
-        for (int dx = -1; dx <= 1; ++dx)
-          p.v[dz + 1][dy + 1][dx + 1] =
-              (dx != 0 && dy != 0 && dz != 0)
-                  ? D(0)
-                  : sm.mu[s3][i][my + dy][mx + dx];
-    }
-    return p;
-  }
-
-  __device__ static inline Patch3<R> tpatch(const Smem& sm, int c, int z,
-                                            int mx, int my) {
-    Patch3<R> p;
-#pragma unroll
-    for (int dz = -1; dz <= 1; ++dz) {
-      const int s3 = slot(z + dz, NMP);
-#pragma unroll
-      for (int dy = -1; dy <= 1; ++dy)
-#pragma unroll
-        for (int dx = -1; dx <= 1; ++dx)
-          p.v[dz + 1][dy + 1][dx + 1] =
-              (dx != 0 && dy != 0 && dz != 0)
-                  ? R(0)
-                  : sm.T[s3][c][my + dy][mx + dx];
-    }
-    return p;
-  }
-
   // Output node (tx, ty) of plane z.
   __device__ static inline void node3(const Smem& sm, const Coef<D>& kd,
                                       const Coef<R>& k, const Bufs<S>& b,
@@ -316,67 +242,55 @@ struct Step3D {
     const int lx = tx + 2, ly = ty + 2, mx = tx + 1, my = ty + 1;
     const Nbr3 nb = make_nbr3(gx, gy, z, k.nx, k.ny, k.nz);
 
-    const Patch3<D> ps = psipatch(sm, z, lx, ly);
-    const D psi_d = ps.v[1][1][1];
+    const int sc[3] = {slot(z - 1, NCP), slot(z, NCP), slot(z + 1, NCP)};
+    const int sm3[3] = {slot(z - 1, NMP), slot(z, NMP), slot(z + 1, NMP)};
+    auto psi_at = [&](int dx, int dy, int dz) {
+      return D(sm.psi[sc[dz + 1]][ly + dy][lx + dx]);
+    };
+    const D psi_d = psi_at(0, 0, 0);
     const R psi = R(psi_d);
     const D psih_d = psi_d > kd.psi_min ? psi_d : kd.psi_min;
-    const R gpsi[3] = {R(grad3<0>(ps)), R(grad3<1>(ps)), R(grad3<2>(ps))};
-    // phi rho on the patch from C and psi
-    Patch3<D> pr;
+    const R gpsi[3] = {R(agrad<0, D>(psi_at)), R(agrad<1, D>(psi_at)),
+                       R(agrad<2, D>(psi_at))};
+    // phi rho at a neighbour: psi sum_i rho_i C_i
+    auto prho_at = [&](int dx, int dy, int dz) {
+      D r = D(0);
 #pragma unroll
-    for (int a = 0; a < 27; ++a) (&pr.v[0][0][0])[a] = D(0);
+      for (int i = 0; i < N; ++i)
+        r += kd.rho[i] * sm.C[sc[dz + 1]][i][ly + dy][lx + dx];
+      return r * psi_at(dx, dy, dz);
+    };
+    const R psirho = R(prho_at(0, 0, 0));
+    const R gprho[3] = {R(agrad<0, D>(prho_at)), R(agrad<1, D>(prho_at)),
+                        R(agrad<2, D>(prho_at))};
     R C[N], gC[N][3], mu[N], gmu[N][3];
 #pragma unroll
     for (int i = 0; i < N; ++i) {
-      const Patch3<D> cp = cpatch(sm, i, z, lx, ly);
-#pragma unroll
-      for (int a = 0; a < 27; ++a)
-        (&pr.v[0][0][0])[a] += kd.rho[i] * (&cp.v[0][0][0])[a];
-      C[i] = R(cp.v[1][1][1]);
-      gC[i][0] = R(grad3<0>(cp));
-      gC[i][1] = R(grad3<1>(cp));
-      gC[i][2] = R(grad3<2>(cp));
-      const Patch3<D> mp = mupatch(sm, i, z, mx, my);
-      mu[i] = R(mp.v[1][1][1]);
-      gmu[i][0] = R(grad3<0>(mp));
-      gmu[i][1] = R(grad3<1>(mp));
-      gmu[i][2] = R(grad3<2>(mp));
+      auto c_at = [&](int dx, int dy, int dz) {
+        return sm.C[sc[dz + 1]][i][ly + dy][lx + dx];
+      };
+      auto mu_at = [&](int dx, int dy, int dz) {
+        return sm.mu[sm3[dz + 1]][i][my + dy][mx + dx];
+      };
+      C[i] = R(c_at(0, 0, 0));
+      gC[i][0] = R(agrad<0, D>(c_at));
+      gC[i][1] = R(agrad<1, D>(c_at));
+      gC[i][2] = R(agrad<2, D>(c_at));
+      mu[i] = R(mu_at(0, 0, 0));
+      gmu[i][0] = R(agrad<0, D>(mu_at));
+      gmu[i][1] = R(agrad<1, D>(mu_at));
+      gmu[i][2] = R(agrad<2, D>(mu_at));
     }
-#pragma unroll
-    for (int a = 0; a < 27; ++a) (&pr.v[0][0][0])[a] *= (&ps.v[0][0][0])[a];
-    const R psirho = R(pr.v[1][1][1]);
-    const R gprho[3] = {R(grad3<0>(pr)), R(grad3<1>(pr)), R(grad3<2>(pr))};
     R grho[3] = {R(0), R(0), R(0)};
 #pragma unroll
     for (int i = 0; i < N; ++i)
 #pragma unroll
       for (int a = 0; a < 3; ++a) grho[a] += k.rho[i] * gC[i][a];
-
-    // own phi C_i (sum of the pulled populations) and phi mu_i = mu_i psi
-    D psiC[N];
-    R fp[N][QF];
-    D f0[N];
-#pragma unroll
-    for (int i = 0; i < N; ++i) {
-      if constexpr (MODE == MODE_INIT) {
-        psiC[i] = psi_d * b.inC[i * n + idx];
-      } else {
-        const S* f = b.fA + (long long)i * QF * n;
-        f0[i] = b.f0A[i * n + idx];
-        D s = f0[i];
-#pragma unroll
-        for (int p = 1; p < QF; ++p) {
-          fp[i][p] = ld<S, R>(f + p * n + nb.src(LF::c[p].x, LF::c[p].y, LF::c[p].z));
-          s += D(fp[i][p]);
-        }
-        psiC[i] = s;
-      }
-    }
     D psimu_d[N];
     R psimu[N];
 #pragma unroll
     for (int i = 0; i < N; ++i) {
-      psimu_d[i] = D(mu[i]) * psih_d;
+      psimu_d[i] = D(sm.mu[sm3[1]][i][my][mx]) * psih_d;
       psimu[i] = R(psimu_d[i]);
     }
     // mass flux m^C (eq. 2.5, Section 2.2)
@@ -414,12 +328,18 @@ struct Step3D {
         if (LG::c[p].z) j[2] += R(LG::c[p].z) * gp[p];
       }
       // -div T^{n-1} with T antisymmetric, components xy, xz, yz
-      const Patch3<R> txy = tpatch(sm, 0, z, mx, my);
-      const Patch3<R> txz = tpatch(sm, 1, z, mx, my);
-      const Patch3<R> tyz = tpatch(sm, 2, z, mx, my);
-      const R divT[3] = {-grad3<1>(txy) - grad3<2>(txz),
-                         grad3<0>(txy) - grad3<2>(tyz),
-                         grad3<0>(txz) + grad3<1>(tyz)};
+      auto txy = [&](int dx, int dy, int dz) {
+        return sm.T[sm3[dz + 1]][0][my + dy][mx + dx];
+      };
+      auto txz = [&](int dx, int dy, int dz) {
+        return sm.T[sm3[dz + 1]][1][my + dy][mx + dx];
+      };
+      auto tyz = [&](int dx, int dy, int dz) {
+        return sm.T[sm3[dz + 1]][2][my + dy][mx + dx];
+      };
+      const R divT[3] = {-agrad<1, R>(txy) - agrad<2, R>(txz),
+                         agrad<0, R>(txy) - agrad<2, R>(tyz),
+                         agrad<0, R>(txz) + agrad<1, R>(tyz)};
       const R Pprev = ld<S, R>(b.hist + (3 * N + 6) * n + idx);
       R Fp[3];
 #pragma unroll
@@ -555,7 +475,23 @@ struct Step3D {
     // ---- phase sets ----------------------------------------------------
 #pragma unroll
     for (int i = 0; i < N; ++i) {
-      const R X[3] = {R(psiC[i]) * u[0], R(psiC[i]) * u[1], R(psiC[i]) * u[2]};
+      // own phi C_i = sum of the pulled populations (Section 3)
+      R fp[QF];
+      D f0 = D(0), psiC;
+      if constexpr (MODE == MODE_INIT) {
+        psiC = psi_d * b.inC[i * n + idx];
+      } else {
+        const S* f = b.fA + (long long)i * QF * n;
+        f0 = b.f0A[i * n + idx];
+        psiC = f0;
+#pragma unroll
+        for (int p = 1; p < QF; ++p) {
+          fp[p] = ld<S, R>(f + p * n +
+                           nb.src(LF::c[p].x, LF::c[p].y, LF::c[p].z));
+          psiC += D(fp[p]);
+        }
+      }
+      const R X[3] = {R(psiC) * u[0], R(psiC) * u[1], R(psiC) * u[2]};
       R V[3] = {R(0), R(0), R(0)};
       if constexpr (MODE != MODE_INIT) {
         R Sv[3];
@@ -574,13 +510,13 @@ struct Step3D {
         }
       }
       const R em = k.eta[i] * psimu[i];
-      const D feq0 = (kd.wf[0] - D(1)) * kd.eta[i] * psimu_d[i] + psiC[i];
+      const D feq0 = (kd.wf[0] - D(1)) * kd.eta[i] * psimu_d[i] + psiC;
       R d[QF];
       S* fdst = b.fB + (long long)i * QF * n;
       if constexpr (MODE == MODE_INIT) {
         b.f0B[i * n + idx] = feq0;
       } else {
-        d[0] = R(f0[i] - feq0);
+        d[0] = R(f0 - feq0);
       }
 #pragma unroll
       for (int p = 1; p < QF; ++p) {
@@ -590,7 +526,7 @@ struct Step3D {
         if constexpr (MODE == MODE_INIT) {
           fdst[p * n + nb.src(cx, cy, cz)] = S(feq);
         } else {
-          d[p] = fp[i][p] - feq;
+          d[p] = fp[p] - feq;
         }
       }
       if constexpr (MODE != MODE_INIT) {
@@ -610,9 +546,9 @@ struct Step3D {
           ms[q] = s * m[q] - (R(1) - R(0.5) * s) * mf[q];
         }
         from_hermite<LF>(ms, del, k.cs2);
-        b.f0B[i * n + idx] = f0[i] - D(del[0]);
+        b.f0B[i * n + idx] = f0 - D(del[0]);
 #pragma unroll
-        for (int p = 1; p < QF; ++p) fdst[p * n + idx] = S(fp[i][p] - del[p]);
+        for (int p = 1; p < QF; ++p) fdst[p * n + idx] = S(fp[p] - del[p]);
       }
 #pragma unroll
       for (int a = 0; a < 3; ++a) b.hist[(3 * i + a) * n + idx] = S(X[a]);
