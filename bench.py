@@ -29,6 +29,8 @@ METRIC = ("MLUPS (all distribution sets) and % of HBM roofline, "
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.json")
 KERNEL_SOURCES = ["paper_2311_10314_amd/csrc/step2d.hip",
+                  "paper_2311_10314_amd/csrc/collide.hpp",
+                  "paper_2311_10314_amd/csrc/common.hpp",
                   "paper_2311_10314_amd/csrc/lattice.hpp",
                   "paper_2311_10314_amd/csrc/coef.hpp"]
 

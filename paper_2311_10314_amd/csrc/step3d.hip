@@ -21,6 +21,7 @@
 #include <hip/hip_runtime.h>
 
 #include "coef.hpp"
+#include "collide.hpp"
 #include "common.hpp"
 #include "kernels.hpp"
 #include "lattice.hpp"
@@ -87,11 +88,11 @@ __device__ inline T adiv_psi_grad(FP&& ps, FC&& c) {
 struct Nbr3 {
   int xm, xp, ym, yp, zm, zp, x, y, z, nx, ny;
   // pull: population with velocity c at (x, y, z) comes from x - c
-  __device__ inline long long src(int cx, int cy, int cz) const {
+  __device__ inline unsigned src(int cx, int cy, int cz) const {
     const int sx = cx == 1 ? xm : (cx == -1 ? xp : x);
     const int sy = cy == 1 ? ym : (cy == -1 ? yp : y);
     const int sz = cz == 1 ? zm : (cz == -1 ? zp : z);
-    return ((long long)sz * ny + sy) * nx + sx;
+    return (unsigned(sz) * unsigned(ny) + unsigned(sy)) * unsigned(nx) + unsigned(sx);
   }
 };
 
@@ -139,23 +140,27 @@ struct Step3D {
                                       int lx, int ly) {
     const int gx = wrap(x0 + lx - 2, k.nx), gy = wrap(y0 + ly - 2, k.ny);
     const int gz = wrap(z, k.nz);
-    const long long idx = ((long long)gz * k.ny + gy) * k.nx + gx;
+    const unsigned idx = (unsigned(gz) * unsigned(k.ny) + unsigned(gy)) * unsigned(k.nx) +
+                         unsigned(gx);
     const S psiS = b.psi[idx];
     const D psi = D(psiS);
     D psiC[N];
     if constexpr (MODE == MODE_INIT) {
 #pragma unroll
-      for (int i = 0; i < N; ++i) psiC[i] = psi * b.inC[i * k.n + idx];
+      for (int i = 0; i < N; ++i) psiC[i] = psi * (b.inC + (long long)i * k.n)[idx];
     } else {
       const Nbr3 nb = make_nbr3(gx, gy, gz, k.nx, k.ny, k.nz);
 #pragma unroll
       for (int i = 0; i < N; ++i) {
+        // phi C_i = sum_p f^i_p (Section 3): moving populations summed in
+        // the storage precision, the float64 rest population added last
         const S* f = b.fA + (long long)i * QF * k.n;
-        D s = b.f0A[i * k.n + idx];
+        R mv = R(0);
 #pragma unroll
         for (int p = 1; p < QF; ++p)
-          s += ld<S, D>(f + p * k.n + nb.src(LF::c[p].x, LF::c[p].y, LF::c[p].z));
-        psiC[i] = s;
+          mv += ld<S, R>(&(f + (long long)p * k.n)[nb.src(LF::c[p].x, LF::c[p].y,
+                                                          LF::c[p].z)]);
+        psiC[i] = (b.f0A + (long long)i * k.n)[idx] + D(mv);
       }
     }
     // C_i = phi C_i / sum_j phi C_j (keeps sum_j C_j = 1 exact)
@@ -176,7 +181,8 @@ struct Step3D {
     const int lx = mx + 1, ly = my + 1;
     const int gx = wrap(x0 + mx - 1, k.nx), gy = wrap(y0 + my - 1, k.ny);
     const int gz = wrap(z, k.nz);
-    const long long idx = ((long long)gz * k.ny + gy) * k.nx + gx;
+    const unsigned idx = (unsigned(gz) * unsigned(k.ny) + unsigned(gy)) * unsigned(k.nx) +
+                         unsigned(gx);
     const int sl[3] = {slot(z - 1, NCP), slot(z, NCP), slot(z + 1, NCP)};
     auto psi_at = [&](int dx, int dy, int dz) {
       return D(sm.psi[sl[dz + 1]][ly + dy][lx + dx]);
@@ -197,7 +203,7 @@ struct Step3D {
     }
     D ct[N];
 #pragma unroll
-    for (int i = 0; i < N - 1; ++i) ct[i] = ld<S, D>(b.ct + i * k.n + idx);
+    for (int i = 0; i < N - 1; ++i) ct[i] = ld<S, D>(&(b.ct + (long long)i * k.n)[idx]);
     ct[N - 1] = D(0);
     D W[N];
 #pragma unroll
@@ -228,7 +234,7 @@ struct Step3D {
     if constexpr (MODE != MODE_INIT) {
 #pragma unroll
       for (int c = 0; c < 3; ++c)
-        sm.T[s3][c][my][mx] = ld<S, R>(b.TA + c * k.n + idx);
+        sm.T[s3][c][my][mx] = ld<S, R>(&(b.TA + (long long)c * k.n)[idx]);
     }
   }
 
@@ -238,7 +244,8 @@ struct Step3D {
                                       int x0, int y0, int z, int tx, int ty) {
     const int gx = x0 + tx, gy = y0 + ty;
     const long long n = k.n;
-    const long long idx = ((long long)z * k.ny + gy) * k.nx + gx;
+    const unsigned idx = (unsigned(z) * unsigned(k.ny) + unsigned(gy)) * unsigned(k.nx) +
+                         unsigned(gx);
     const int lx = tx + 2, ly = ty + 2, mx = tx + 1, my = ty + 1;
     const Nbr3 nb = make_nbr3(gx, gy, z, k.nx, k.ny, k.nz);
 
@@ -316,12 +323,13 @@ struct Step3D {
     R sum_gm = R(0);
     if constexpr (MODE == MODE_INIT) {
 #pragma unroll
-      for (int a = 0; a < 3; ++a) u[a] = b.inU ? R(b.inU[a * n + idx]) : R(0);
+      for (int a = 0; a < 3; ++a) u[a] = b.inU ? R((b.inU + a * n)[idx]) : R(0);
     } else {
       R j[3] = {R(0), R(0), R(0)};
 #pragma unroll
       for (int p = 0; p < QG; ++p) {
-        gp[p] = ld<S, R>(b.gA + p * n + nb.src(LG::c[p].x, LG::c[p].y, LG::c[p].z));
+        gp[p] = ld<S, R>(&(b.gA + (long long)p * n)[nb.src(LG::c[p].x, LG::c[p].y,
+                                                            LG::c[p].z)]);
         if (p > 0) sum_gm += gp[p];
         if (LG::c[p].x) j[0] += R(LG::c[p].x) * gp[p];
         if (LG::c[p].y) j[1] += R(LG::c[p].y) * gp[p];
@@ -340,7 +348,7 @@ struct Step3D {
       const R divT[3] = {-agrad<1, R>(txy) - agrad<2, R>(txz),
                          agrad<0, R>(txy) - agrad<2, R>(tyz),
                          agrad<0, R>(txz) + agrad<1, R>(tyz)};
-      const R Pprev = ld<S, R>(b.hist + (3 * N + 6) * n + idx);
+      const R Pprev = ld<S, R>(&(b.hist + (long long)(3 * N + 6) * n)[idx]);
       R Fp[3];
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
@@ -372,7 +380,7 @@ struct Step3D {
     if constexpr (MODE != MODE_INIT) {
 #pragma unroll
       for (int q = 0; q < 6; ++q)
-        dtY[q] = Y[q] - ld<S, R>(b.hist + (3 * N + q) * n + idx);
+        dtY[q] = Y[q] - ld<S, R>(&(b.hist + (long long)(3 * N + q) * n)[idx]);
     }
     R nu = R(0);
 #pragma unroll
@@ -399,16 +407,15 @@ struct Step3D {
     const R uvec[3] = {u[0], u[1], u[2]};
     if constexpr (MODE == MODE_MOMENTS) {
 #pragma unroll
-      for (int i = 0; i < N; ++i) b.outC[i * n + idx] = double(C[i]);
+      for (int i = 0; i < N; ++i) (b.outC + i * n)[idx] = double(C[i]);
 #pragma unroll
-      for (int a = 0; a < 3; ++a) b.outU[a * n + idx] = double(uvec[a]);
+      for (int a = 0; a < 3; ++a) (b.outU + a * n)[idx] = double(uvec[a]);
       b.outP[idx] = double(P);
       return;
     }
 
-    // ---- flow set ------------------------------------------------------
-    {
-      R d[QG];
+    // ---- flow set: equilibrium (eqs. 3.8, 3.11), source (3.10, 3.12) ---
+    if constexpr (MODE == MODE_INIT) {
 #pragma unroll
       for (int p = 0; p < QG; ++p) {
         const int cx = LG::c[p].x, cy = LG::c[p].y, cz = LG::c[p].z;
@@ -422,142 +429,91 @@ struct Step3D {
                                k.inv_cs2 +
                            h2);
         if (p == 0) geq -= psiP * k.inv_cs2;  // stored as g_0 - rho0
-        if constexpr (MODE == MODE_INIT) {
-          d[p] = geq;
-        } else {
-          d[p] = gp[p] - geq;
-        }
+        // the buffers hold pre-streaming values: place g_p(x) where the
+        // next pull reads it, at x - c_p
+        (b.gB + (long long)p * n)[nb.src(cx, cy, cz)] = S(geq);
       }
-      if constexpr (MODE == MODE_INIT) {
+    } else {
+      const R ub = u[0] * gprho[0] + u[1] * gprho[1] + u[2] * gprho[2];
+      // M^{2G} (eq. 3.12) with the scalar u.grad(phi rho) on the diagonal
+      const R M[6] = {
+          dtY[0] + R(2) * k.cs2 * u[0] * gprho[0] + k.one_m3cs2 * ub,
+          dtY[1] + k.cs2 * (u[0] * gprho[1] + gprho[0] * u[1]),
+          dtY[2] + k.cs2 * (u[0] * gprho[2] + gprho[0] * u[2]),
+          dtY[3] + R(2) * k.cs2 * u[1] * gprho[1] + k.one_m3cs2 * ub,
+          dtY[4] + k.cs2 * (u[1] * gprho[2] + gprho[1] * u[2]),
+          dtY[5] + R(2) * k.cs2 * u[2] * gprho[2] + k.one_m3cs2 * ub};
+      const R a0 = psi * (u[0] * grho[0] + u[1] * grho[1] + u[2] * grho[2]);
+      const R J[3] = {psirho * u[0], psirho * u[1], psirho * u[2]};
+      R del[QG];
+      collide_flow<LG>(gp, J, A, psiP, M, a0, F, s21, s22, k.sg, k.q4, k.cs2,
+                       k.inv_cs2, del);
 #pragma unroll
-        for (int p = 0; p < QG; ++p)
-          b.gB[p * n + nb.src(LG::c[p].x, LG::c[p].y, LG::c[p].z)] = S(d[p]);
-      } else {
-        const R ub = u[0] * gprho[0] + u[1] * gprho[1] + u[2] * gprho[2];
-        // M^{2G} (eq. 3.12) with the scalar u.grad(phi rho) on the diagonal
-        const R M[6] = {
-            dtY[0] + R(2) * k.cs2 * u[0] * gprho[0] + k.one_m3cs2 * ub,
-            dtY[1] + k.cs2 * (u[0] * gprho[1] + gprho[0] * u[1]),
-            dtY[2] + k.cs2 * (u[0] * gprho[2] + gprho[0] * u[2]),
-            dtY[3] + R(2) * k.cs2 * u[1] * gprho[1] + k.one_m3cs2 * ub,
-            dtY[4] + k.cs2 * (u[1] * gprho[2] + gprho[1] * u[2]),
-            dtY[5] + R(2) * k.cs2 * u[2] * gprho[2] + k.one_m3cs2 * ub};
-        const R a0 = psi * (u[0] * grho[0] + u[1] * grho[1] + u[2] * grho[2]);
-        R G[QG];
-#pragma unroll
-        for (int p = 0; p < QG; ++p) {
-          const int cx = LG::c[p].x, cy = LG::c[p].y, cz = LG::c[p].z;
-          const R h2 = (M[0] * (R(cx * cx) - k.cs2) + M[3] * (R(cy * cy) - k.cs2) +
-                        M[5] * (R(cz * cz) - k.cs2)) *
-                           k.h2diag +
-                       (M[1] * R(cx * cy) + M[2] * R(cx * cz) + M[4] * R(cy * cz)) *
-                           k.h2off;
-          G[p] = k.wg[p] * (a0 +
-                            (R(cx) * F[0] + R(cy) * F[1] + R(cz) * F[2]) *
-                                k.inv_cs2 +
-                            h2);
-        }
-        R m[QG], mg[QG], ms[QG], del[QG];
-        to_hermite<LG>(d, m, k.cs2);
-        to_hermite<LG>(G, mg, k.cs2);
-#pragma unroll
-        for (int q = 0; q < QG; ++q) {
-          const int grp = LG::rows[q].group;
-          const R s = grp == GR21 ? s21 : (grp == GR22 ? s22 : k.sg[grp]);
-          ms[q] = s * m[q] - (R(1) - R(0.5) * s) * mg[q];
-        }
-        from_hermite<LG>(ms, del, k.cs2);
-#pragma unroll
-        for (int p = 0; p < QG; ++p) b.gB[p * n + idx] = S(gp[p] - del[p]);
-      }
+      for (int p = 0; p < QG; ++p) (b.gB + (long long)p * n)[idx] = S(gp[p] - del[p]);
     }
 
-    // ---- phase sets ----------------------------------------------------
+    // ---- phase sets: equilibrium (3.5), source (3.6, 3.7), collision ---
 #pragma unroll
     for (int i = 0; i < N; ++i) {
-      // own phi C_i = sum of the pulled populations (Section 3)
-      R fp[QF];
-      D f0 = D(0), psiC;
+      const S* fsrc = b.fA + (long long)i * QF * n;
+      S* fdst = b.fB + (long long)i * QF * n;
       if constexpr (MODE == MODE_INIT) {
-        psiC = psi_d * b.inC[i * n + idx];
-      } else {
-        const S* f = b.fA + (long long)i * QF * n;
-        f0 = b.f0A[i * n + idx];
-        psiC = f0;
+        const D psiC = psi_d * (b.inC + (long long)i * n)[idx];
+        const R X[3] = {R(psiC) * u[0], R(psiC) * u[1], R(psiC) * u[2]};
+        const R em = k.eta[i] * psimu[i];
+        // f^eq_0 = (w_0 - 1) eta phi mu + phi C (float64 rest plane)
+        (b.f0B + (long long)i * n)[idx] =
+            (kd.wf[0] - D(1)) * kd.eta[i] * psimu_d[i] + psiC;
 #pragma unroll
         for (int p = 1; p < QF; ++p) {
-          fp[p] = ld<S, R>(f + p * n +
-                           nb.src(LF::c[p].x, LF::c[p].y, LF::c[p].z));
-          psiC += D(fp[p]);
+          const int cx = LF::c[p].x, cy = LF::c[p].y, cz = LF::c[p].z;
+          const R feq = k.wf[p] * (em + (R(cx) * X[0] + R(cy) * X[1] +
+                                         R(cz) * X[2]) * k.inv_cs2);
+          (fdst + (long long)p * n)[nb.src(cx, cy, cz)] = S(feq);
         }
-      }
-      const R X[3] = {R(psiC) * u[0], R(psiC) * u[1], R(psiC) * u[2]};
-      R V[3] = {R(0), R(0), R(0)};
-      if constexpr (MODE != MODE_INIT) {
-        R Sv[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) (b.hist + (long long)(3 * i + a) * n)[idx] = S(X[a]);
+      } else {
+        // own phi C_i = sum of the pulled populations (Section 3): moving
+        // populations summed in the storage precision, the float64 rest
+        // population added last
+        R fp[QF];
+        fp[0] = R(0);
+        R mv = R(0);
+#pragma unroll
+        for (int p = 1; p < QF; ++p) {
+          fp[p] = ld<S, R>(&(fsrc + (long long)p * n)[nb.src(LF::c[p].x, LF::c[p].y,
+                                                              LF::c[p].z)]);
+          mv += fp[p];
+        }
+        const D f0 = (b.f0A + (long long)i * n)[idx];
+        const R psiC = R(f0 + D(mv));
+        const R X[3] = {psiC * u[0], psiC * u[1], psiC * u[2]};
+        // S_i (eq. 3.7) and V = d_t(phi C_i u) + c_s^2 eta (mu grad psi - S_i)
+        R V[3];
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
           R sa = (C[i] * Cs[i] - R(1)) * gmu[i][a];
 #pragma unroll
           for (int j = 0; j < N; ++j)
             if (j != i) sa -= C[i] * C[j] * gmu[j][a];
-          Sv[a] = psi * sa;
+          const R dX = X[a] - ld<S, R>(&(b.hist + (long long)(3 * i + a) * n)[idx]);
+          V[a] = dX + k.cs2 * k.eta[i] * (mu[i] * gpsi[a] - psi * sa);
         }
+        R del[QF];
+        collide_phase<LF>(fp, k.eta[i] * psimu[i], X, V, k.sf, k.cs2, del);
+        (b.f0B + (long long)i * n)[idx] = f0 - D(del[0]);
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-          const R dX = X[a] - ld<S, R>(b.hist + (3 * i + a) * n + idx);
-          V[a] = dX + k.cs2 * k.eta[i] * (mu[i] * gpsi[a] - Sv[a]);
-        }
+        for (int p = 1; p < QF; ++p) (fdst + (long long)p * n)[idx] = S(fp[p] - del[p]);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) (b.hist + (long long)(3 * i + a) * n)[idx] = S(X[a]);
       }
-      const R em = k.eta[i] * psimu[i];
-      const D feq0 = (kd.wf[0] - D(1)) * kd.eta[i] * psimu_d[i] + psiC;
-      R d[QF];
-      S* fdst = b.fB + (long long)i * QF * n;
-      if constexpr (MODE == MODE_INIT) {
-        b.f0B[i * n + idx] = feq0;
-      } else {
-        d[0] = R(f0 - feq0);
-      }
-#pragma unroll
-      for (int p = 1; p < QF; ++p) {
-        const int cx = LF::c[p].x, cy = LF::c[p].y, cz = LF::c[p].z;
-        const R feq = k.wf[p] * (em + (R(cx) * X[0] + R(cy) * X[1] + R(cz) * X[2]) *
-                                          k.inv_cs2);
-        if constexpr (MODE == MODE_INIT) {
-          fdst[p * n + nb.src(cx, cy, cz)] = S(feq);
-        } else {
-          d[p] = fp[p] - feq;
-        }
-      }
-      if constexpr (MODE != MODE_INIT) {
-        R Fs[QF];
-#pragma unroll
-        for (int p = 0; p < QF; ++p) {
-          const int cx = LF::c[p].x, cy = LF::c[p].y, cz = LF::c[p].z;
-          Fs[p] = k.wf[p] * (R(cx) * V[0] + R(cy) * V[1] + R(cz) * V[2]) *
-                  k.inv_cs2;
-        }
-        R m[QF], mf[QF], ms[QF], del[QF];
-        to_hermite<LF>(d, m, k.cs2);
-        to_hermite<LF>(Fs, mf, k.cs2);
-#pragma unroll
-        for (int q = 0; q < QF; ++q) {
-          const R s = k.sf[LF::rows[q].group];
-          ms[q] = s * m[q] - (R(1) - R(0.5) * s) * mf[q];
-        }
-        from_hermite<LF>(ms, del, k.cs2);
-        b.f0B[i * n + idx] = f0 - D(del[0]);
-#pragma unroll
-        for (int p = 1; p < QF; ++p) fdst[p * n + idx] = S(fp[p] - del[p]);
-      }
-#pragma unroll
-      for (int a = 0; a < 3; ++a) b.hist[(3 * i + a) * n + idx] = S(X[a]);
     }
 #pragma unroll
-    for (int q = 0; q < 6; ++q) b.hist[(3 * N + q) * n + idx] = S(Y[q]);
-    b.hist[(3 * N + 6) * n + idx] = S(P);
+    for (int q = 0; q < 6; ++q) (b.hist + (long long)(3 * N + q) * n)[idx] = S(Y[q]);
+    (b.hist + (long long)(3 * N + 6) * n)[idx] = S(P);
 #pragma unroll
-    for (int c = 0; c < 3; ++c) b.TB[c * n + idx] = S(Tn[c]);
+    for (int c = 0; c < 3; ++c) (b.TB + (long long)c * n)[idx] = S(Tn[c]);
   }
 
   __device__ static void run(const Coef<D>& kd, const Coef<R>& k,

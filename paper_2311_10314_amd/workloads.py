@@ -80,8 +80,12 @@ def droplet(r, radius, eps):
 
 
 def default_params(dim, N, **kw):
+    """Parameters shared by the workloads. The penalty coefficient of
+    (1 - psi) u is 0.5 per step: the printed 1 / eps0^3 taken in lattice
+    units (0.013 for eps0 = 4.2) lets an interface that touches a flat wall
+    grow an instability inside the wall layer within a few hundred steps."""
     p = dict(d0=0.4, eps=5.0, eps0=2.0 * math.sqrt(2.0) * PSI_WIDTH, m0=0.05,
-             rho0=1.0, psi_min=1e-30,
+             rho0=1.0, psi_min=1e-30, lam=0.5,
              sigma=[[0.0 if i == j else 0.01 for j in range(N)]
                     for i in range(N)],
              rho=[1.0] * N, nu=[0.1] * N,
