@@ -4,10 +4,14 @@ python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 512] [--skip-cpu]
 
 Workload: the 2D porous medium of the paper's setting (512 x 512 periodic
 box, 40 seeded disks with radii U[10, 30], three vertical phase bands,
-per-obstacle contact angles U[45, 135] deg, densities 1:10:100, body
-acceleration 1e-6), N = 3 phase sets + 1 flow set on D2Q9. One "step" is one
+per-obstacle contact angles U[45, 135] deg, densities 1:10:100, body force
+density 1e-6), N = 3 phase sets + 1 flow set on D2Q9. One "step" is one
 time step of the whole scheme (one fused kernel launch). Both FP32 and FP64
 are timed; the JSON `value` is the FP32 figure and `fp64` holds the other.
+The 3D leg (`sphere3d`: a droplet impacting a sphere, D3Q15 phase sets and a
+D3Q19 flow set, N = 2, n^3 box) is timed in FP32, FP64 and the two 16-bit
+population storages, each with its error against the FP64 oracle on the
+same case at 32^3.
 
 MLUPS counts lattice-node updates per second, each update covering all N + 1
 distribution sets. `roofline.achieved` is the algorithmic HBM bytes of one
@@ -35,16 +39,21 @@ KERNEL_SOURCES = ["paper_2311_10314_amd/csrc/step2d.hip",
                   "paper_2311_10314_amd/csrc/coef.hpp"]
 
 
-def algorithmic_bytes_per_node(N, dim, Qf, Qg, esz):
+PREC_BYTES = {"fp64": (8, 8), "fp32": (4, 4), "fp16": (2, 4), "bf16": (2, 4)}
+
+
+def algorithmic_bytes_per_node(N, dim, Qf, Qg, precision):
     """Populations (N Qf + Qg) read and written once (the N rest populations
-    of the phase sets are float64 in both precisions), history
+    of the phase sets are float64 in every precision, the moving ones and the
+    flow set in the population storage type), history
     (N d + d(d+1)/2 + 1 in place, d(d-1)/2 double-buffered) read and written
-    once, psi and N-1 wetting cosines read once."""
-    pops = (N * (Qf - 1) + Qg) * 2 * esz + N * 2 * 8
+    once, psi and N-1 wetting cosines read once (field storage type)."""
+    pesz, fesz = PREC_BYTES[precision]
+    pops = (N * (Qf - 1) + Qg) * 2 * pesz + N * 2 * 8
     hist = (N * dim + dim * (dim + 1) // 2 + 1) * 2
     tens = (dim * (dim - 1) // 2) * 2
     static = 1 + (N - 1)
-    return pops + (hist + tens + static) * esz
+    return pops + (hist + tens + static) * fesz
 
 
 def kernel_source_hash():
@@ -75,25 +84,90 @@ def make_workload(n):
     return W.porous_bands_2d(n=n)
 
 
-def sphere_leg(n, steps, warmup, torch, precisions=("fp32", "fp64")):
+def sphere_leg(n, steps, warmup, torch, precisions):
     """3D leg: the sphere / impacting-droplet box (D3Q15 phase sets, D3Q19
-    flow set, N = 2) at n^3."""
+    flow set, N = 2) at n^3, with each precision's error against the FP64
+    oracle after 40 steps of the same case at 32^3."""
+    import numpy as np
+
     from paper_2311_10314_amd import workloads as W
+    from paper_2311_10314_amd.ddcc import Sim
     wl = W.droplet_impact_sphere_3d(n=n)
+    small = W.droplet_impact_sphere_3d(n=32)
+    ref = None
     out = {}
     for prec in precisions:
-        esz = 4 if prec == "fp32" else 8
         sim, ms, drift = time_gpu(wl, prec, steps, warmup, torch)
         sim.close()
-        bpn = algorithmic_bytes_per_node(2, 3, 15, 19, esz)
+        bpn = algorithmic_bytes_per_node(2, 3, 15, 19, prec)
         achieved = bpn * wl.nodes / (ms * 1e-3) / 1e9
+        if ref is None:
+            import oracle
+            prm, geo, st = oracle.from_workload(small)
+            st = oracle.run(prm, geo, st, 40)
+            ref = oracle.moments(prm, geo, st)
+        s2 = Sim.from_workload(small, prec)
+        s2.step(40)
+        C, u, _ = s2.read_moments()
+        s2.close()
+        Co, uo, _ = ref
+        err = {"rel_linf_C": max(float(np.abs(C[i] - Co[i]).max() /
+                                       np.abs(Co[i]).max())
+                                 for i in range(len(Co))),
+               "rel_linf_u": float(np.abs(u - uo).max() / np.abs(uo).max()),
+               "case": "32^3, 40 steps"}
         out[prec] = {"value": wl.nodes / (ms * 1e-3) / 1e6,
                      "unit": "MLUPS", "ms_per_step": ms, "mass_drift": drift,
                      "bytes_per_node": bpn, "achieved_GBs": achieved,
-                     "frac": achieved / HBM_PEAK_GBS, "steps": steps}
-        print("  sphere3d %d^3 %s: %.4f ms/step, %.0f MLUPS, %.0f GB/s" % (
-            n, prec, ms, out[prec]["value"], achieved), file=sys.stderr,
-            flush=True)
+                     "frac": achieved / HBM_PEAK_GBS, "steps": steps,
+                     "error_vs_oracle": err}
+        print("  sphere3d %d^3 %s: %.4f ms/step, %.0f MLUPS, %.0f GB/s%s" % (
+            n, prec, ms, out[prec]["value"], achieved,
+            ", C %.1e u %.1e" % (err["rel_linf_C"], err["rel_linf_u"])),
+            file=sys.stderr, flush=True)
+    return out
+
+
+def batched_leg(count, steps, torch, graph_steps=50):
+    """Batched leg: `count` independent 2D N = 2 instances of uneven sizes
+    (sides from {64, 96, 128, 192, 256}, seeded disks and droplets) advanced
+    by one persistent launch per step, the tile height picked by the
+    library's autotuner and the steps replayed from HIP graphs of
+    `graph_steps` steps. FP32."""
+    import numpy as np
+
+    from paper_2311_10314_amd import workloads as W
+    from paper_2311_10314_amd.ddcc import Batch
+    wls = W.batched_instances(count)
+    stream = torch.cuda.Stream()
+    b = Batch.from_workloads(wls, "fp32", stream=stream.cuda_stream)
+    ty = b.autotune(5)
+    b.set_graph(graph_steps)
+    m0 = [b.mass(i) for i in range(count)]
+    b.step(2 * graph_steps)
+    b.sync()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record(stream)
+    b.step(steps)
+    t1.record(stream)
+    t1.synchronize()
+    ms = t0.elapsed_time(t1) / steps
+    drift = max(float((np.abs(b.mass(i) - m0[i]) / np.abs(m0[i])).max())
+                for i in range(count))
+    nodes = b.nodes
+    b.close()
+    bpn = algorithmic_bytes_per_node(2, 2, 9, 9, "fp32")
+    achieved = bpn * nodes / (ms * 1e-3) / 1e9
+    out = {"value": nodes / (ms * 1e-3) / 1e6, "unit": "MLUPS",
+           "instances": count, "nodes": nodes, "ms_per_step": ms,
+           "steps": steps, "tile_rows": ty, "graph_steps": graph_steps,
+           "mass_drift": drift, "bytes_per_node": bpn,
+           "achieved_GBs": achieved, "frac": achieved / HBM_PEAK_GBS}
+    print("  batched %d instances (%d nodes): %.4f ms/step, %.0f MLUPS, "
+          "%.0f GB/s, tile rows %d" % (count, nodes, ms, out["value"],
+                                       achieved, ty), file=sys.stderr,
+          flush=True)
     return out
 
 
@@ -186,12 +260,15 @@ def main():
     ap.add_argument("--steps", type=int, default=20000)
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--n", type=int, default=512)
-    ap.add_argument("--cpu-steps", type=int, default=8)
+    ap.add_argument("--cpu-steps", type=int, default=64)
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--tile", type=int, default=0)
-    ap.add_argument("--sphere", type=int, default=0,
+    ap.add_argument("--sphere", type=int, default=256,
                     help="also time the 3D sphere box at this n (0: skip)")
-    ap.add_argument("--sphere-steps", type=int, default=200)
+    ap.add_argument("--sphere-steps", type=int, default=100)
+    ap.add_argument("--batch", type=int, default=256,
+                    help="also time this many batched instances (0: skip)")
+    ap.add_argument("--batch-steps", type=int, default=200)
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--precision", default="both",
                     choices=["both", "fp32", "fp64"])
@@ -220,7 +297,7 @@ def main():
         sim, ms, drift = time_gpu(wl, prec, a.steps, a.warmup, torch,
                                   a.tile)
         sim.close()
-        bpn = algorithmic_bytes_per_node(N, 2, 9, 9, esz)
+        bpn = algorithmic_bytes_per_node(N, 2, 9, 9, prec)
         per_launch = bpn * wl.nodes
         achieved = per_launch / (ms * 1e-3) / 1e9
         traffic = measured_traffic(prec)
@@ -244,7 +321,12 @@ def main():
         print("timing the 3D sphere box at %d^3" % a.sphere, file=sys.stderr,
               flush=True)
         sphere = sphere_leg(a.sphere, a.sphere_steps, 10, torch,
-                            tuple(p for p, _ in precs))
+                            tuple(p for p, _ in precs) + ("fp16", "bf16"))
+    batched = None
+    if a.batch:
+        print("timing %d batched instances" % a.batch, file=sys.stderr,
+              flush=True)
+        batched = batched_leg(a.batch, a.batch_steps, torch)
     err = None
     cpu = None
     if not a.skip_cpu:
@@ -253,7 +335,8 @@ def main():
         err = error_vs_oracle(wl, 10)
         cpu = cpu_baseline(wl, a.cpu_steps)
     if "fp32" not in res:
-        print(json.dumps({"fp64": res["fp64"], "sphere3d": sphere}))
+        print(json.dumps({"fp64": res["fp64"], "sphere3d": sphere,
+                          "batched": batched}))
         return 0
     f32 = res["fp32"]
     line = {
@@ -273,6 +356,7 @@ def main():
         "error_vs_oracle": err,
         "fp64": res.get("fp64"),
         "sphere3d": sphere,
+        "batched": batched,
     }
     print(json.dumps(line), flush=True)
     return 0

@@ -55,9 +55,17 @@ extern "C" {
 #define DDCC_D3Q15 2
 #define DDCC_D3Q19 3
 
-/* Storage / arithmetic precision of the populations and history. */
+/* Storage / arithmetic precision of the populations and history. In every
+ * precision the rest populations of the phase sets are float64 and take back
+ * the storage rounding of the node's moving populations, so the mass of each
+ * phase is conserved to the rounding of the arithmetic; the flow set's rest
+ * population is stored as the deviation g_0 - rho0. */
 #define DDCC_FP64 0  /* float64 storage, float64 arithmetic              */
 #define DDCC_FP32 1  /* float32 storage, float32 arithmetic              */
+#define DDCC_FP16 2  /* moving populations in IEEE half, history, T and
+                        geometry in float32, float32 arithmetic          */
+#define DDCC_BF16 3  /* moving populations in bfloat16, otherwise as
+                        DDCC_FP16                                        */
 
 #define DDCC_MAX_PHASES 4
 
@@ -77,7 +85,7 @@ typedef struct ddcc_params {
   int nphase;       /* N, 2 <= N <= DDCC_MAX_PHASES                          */
   int lattice_f;    /* velocity set of the phase sets (DDCC_D2Q9 / D3Q15)    */
   int lattice_g;    /* velocity set of the flow set   (DDCC_D2Q9 / D3Q19)    */
-  int precision;    /* DDCC_FP64 or DDCC_FP32                                */
+  int precision;    /* DDCC_FP64, DDCC_FP32, DDCC_FP16 or DDCC_BF16          */
   double d0;        /* c_s^2 / c^2, inside the lattices' positive-weight range */
   double eps;       /* fluid-fluid interface width (cells), Section 2.1       */
   double m0;        /* mobility of eq. (2.5)                                  */
@@ -158,7 +166,10 @@ int ddcc_load(ddcc_ctx* ctx, const void* buf, size_t bytes);
 int ddcc_sync(ddcc_ctx* ctx);
 
 /* Kernel launch shape of the step kernel: tile (tx, ty) of nodes per
- * workgroup; 0 keeps the default. Takes effect on the next ddcc_step. */
+ * workgroup; 0 keeps the default. tx is 64 (one wavefront per row); ty is
+ * 2, 4, 8 or 16 in 2D (default 8) and 2 or 4 in 3D (default 4). Any other
+ * value returns DDCC_E_INVAL. Takes effect on the next ddcc_step; results
+ * do not depend on the tile. */
 int ddcc_set_tile(ddcc_ctx* ctx, int tx, int ty);
 
 /* Message of the last failed call on ctx (never NULL; "" if none). */
@@ -169,6 +180,76 @@ void ddcc_destroy(ddcc_ctx* ctx);
 
 /* Library version string. */
 const char* ddcc_version(void);
+
+/* ---- Batches of independent boxes -----------------------------------------
+ * Many independent 2D D2Q9 instances of the same method and parameters, on
+ * grids of different sizes, advanced together: one persistent kernel launch
+ * per time step drains a queue of (instance, tile) work items, and
+ * ddcc_batch_set_graph captures groups of steps in a HIP graph. Each
+ * instance's state, inputs and outputs are exactly those of a single context
+ * of its size (same layouts as the single-context calls, per instance).
+ * Every plane of every device field holds all instances one after another,
+ * so the batch owns one allocation per field. */
+typedef struct ddcc_batch ddcc_batch;
+
+/* Creates a batch of count instances with grids nx[i] x ny[i] (host
+ * arrays, copied) and the method parameters of *params (dim must be 2; its
+ * nx, ny, nz are ignored). hip_stream as for ddcc_create; NULL creates a
+ * stream of the library's own (the legacy default stream cannot be
+ * captured). Total nodes at most 2^29. Errors: DDCC_E_INVAL,
+ * DDCC_E_UNSUPPORTED (dim != 2), DDCC_E_NOMEM, DDCC_E_HIP. */
+int ddcc_batch_create(const ddcc_params* params, int count, const int* nx,
+                      const int* ny, void* hip_stream, ddcc_batch** out);
+
+/* Geometry of instance i: psi [ny_i][nx_i] in [0, 1] and the N-1 wetting
+ * cosines cos theta_iN [N-1][ny_i][nx_i] in [-1, 1] (NULL: 90 degrees).
+ * Resets the instance's fields (init_fields again before stepping). */
+int ddcc_batch_init_geometry(ddcc_batch* b, int i, const double* psi,
+                             const double* cos_theta_iN);
+
+/* Initial C [N][ny_i][nx_i], u [2][ny_i][nx_i] (NULL: 0), P (NULL: 0) of
+ * instance i, populations at equilibrium (as ddcc_init_fields).
+ * DDCC_E_STATE before its geometry. Synchronises the batch stream. */
+int ddcc_batch_init_fields(ddcc_batch* b, int i, const double* C,
+                           const double* u, const double* P);
+
+/* Advances every instance by nsteps time steps (asynchronous on the batch
+ * stream). DDCC_E_STATE unless every instance has its fields. */
+int ddcc_batch_step(ddcc_batch* b, int64_t nsteps);
+
+/* C, u, P of instance i at the current step (layouts as init_fields; NULL
+ * skips). Synchronises. */
+int ddcc_batch_read_moments(ddcc_batch* b, int i, double* C, double* u,
+                            double* P);
+
+/* Per-phase totals of instance i, float64 (as ddcc_mass). Synchronises. */
+int ddcc_batch_mass(ddcc_batch* b, int i, double* mass);
+
+/* Tile height of the step kernel: 4, 8 (default) or 16 rows of 64 nodes. */
+int ddcc_batch_set_tile(ddcc_batch* b, int ty);
+
+/* Times `steps` steps with each tile height and keeps the fastest; the
+ * state is restored afterwards (the trial steps are not counted). The
+ * chosen height is written to *ty_out if not NULL. Needs every instance's
+ * fields; allocates a temporary copy of the state. */
+int ddcc_batch_autotune(ddcc_batch* b, int steps, int* ty_out);
+
+/* Steps per captured HIP graph: 0 (default) launches every step directly;
+ * an even number in [2, 1024] replays graphs of that many steps (the rest
+ * of a ddcc_batch_step call is launched directly). */
+int ddcc_batch_set_graph(ddcc_batch* b, int steps_per_graph);
+
+/* Waits for the batch stream. */
+int ddcc_batch_sync(ddcc_batch* b);
+
+/* Steps taken since the batch was created (-1 for NULL). */
+int64_t ddcc_batch_time(const ddcc_batch* b);
+
+/* Message of the last failed call on b (never NULL). */
+const char* ddcc_batch_last_error(const ddcc_batch* b);
+
+/* Releases the batch and its device memory; NULL is a no-op. */
+void ddcc_batch_destroy(ddcc_batch* b);
 
 #ifdef __cplusplus
 }

@@ -18,6 +18,6 @@ def from_workload(wl):
     p = dict(wl.params)
     prm = Params(dim=wl.dim, lattice_f=wl.lattice_f, lattice_g=wl.lattice_g,
                  **p)
-    geo = Geometry(prm, wl.psi, wl.cos_theta_iN)
+    geo = Geometry(prm, wl.psi, wl.cos_theta_iN, walls=wl.walls)
     st = init_state(prm, geo, wl.C0, wl.u0, wl.P0)
     return prm, geo, st

@@ -148,31 +148,54 @@ def div_tensor(T, d):
 # --------------------------------------------------------------------------
 # Static geometry
 # --------------------------------------------------------------------------
-class Geometry:
-    """psi, psi_hat = max(psi, psi_min), grad psi, |grad psi| and the
-    per-node contact-angle cosines cos theta_jq of eq. (2.9)."""
+def pair_cosines(prm, cos_theta_iN, shape):
+    """eq. (2.9): cos th_ij = (s_iN cos th_iN - s_jN cos th_jN) / s_ij for
+    every pair i != j, from the N - 1 angles theta_iN measured against the
+    N-th phase (its own entry cos th_NN is absent, sigma_NN = 0)."""
+    N = prm.N
+    ct = np.zeros((N,) + shape)
+    if N > 1:
+        ct[:N - 1] = np.array(cos_theta_iN, dtype=np.float64).reshape(
+            (N - 1,) + shape)
+    sg = prm.sigma
+    out = np.zeros((N, N) + shape)
+    for i in range(N):
+        for j in range(N):
+            if i != j:
+                out[i, j] = (sg[i, N - 1] * ct[i] - sg[j, N - 1] * ct[j]) \
+                    / sg[i, j]
+    return out
 
-    def __init__(self, prm, psi, cos_theta_iN):
+
+class Geometry:
+    """psi, psi_hat = max(psi, psi_min), grad psi, |grad psi| and, per wall,
+    the contact-angle cosines cos theta_jq of eq. (2.9) with the |grad psi_k|
+    that weights them in the wetting term of eq. (2.14).
+
+    One wall: psi and its angles. Several walls (Section 4.5): `walls` is a
+    list of (psi_k, cos_theta_iN^k); then psi = prod_k psi_k and the wetting
+    term sums cos theta^k_jq |grad psi_k| over the walls."""
+
+    def __init__(self, prm, psi, cos_theta_iN, walls=None):
         d = prm.dim
-        self.psi = np.array(psi, dtype=np.float64)
+        if walls is None:
+            walls = [(psi, cos_theta_iN)]
+            self.psi = np.array(psi, dtype=np.float64)
+        else:
+            self.psi = np.ones(np.shape(walls[0][0]))
+            for psi_k, _ in walls:
+                self.psi = self.psi * np.array(psi_k, dtype=np.float64)
         # Reading: division by psi uses psi_hat = max(psi, psi_min).
         self.psi_hat = np.maximum(self.psi, prm.psi_min)
         self.grad_psi = grad(self.psi, d)
         self.abs_grad_psi = np.sqrt((self.grad_psi ** 2).sum(axis=0))
-        N = prm.N
-        ct = np.zeros((N,) + self.psi.shape)
-        if N > 1:
-            ct[:N - 1] = np.array(cos_theta_iN, dtype=np.float64).reshape(
-                (N - 1,) + self.psi.shape)
-        # eq. (2.9): cos th_ij = (s_iN cos th_iN - s_jN cos th_jN) / s_ij,
-        # with the N-th phase's own entry cos th_NN absent (sigma_NN = 0).
-        sg = prm.sigma
-        self.cos_theta = np.zeros((N, N) + self.psi.shape)
-        for i in range(N):
-            for j in range(N):
-                if i != j:
-                    self.cos_theta[i, j] = (sg[i, N - 1] * ct[i]
-                                            - sg[j, N - 1] * ct[j]) / sg[i, j]
+        self.walls = []
+        for psi_k, ct_k in walls:
+            pk = np.array(psi_k, dtype=np.float64)
+            g = grad(pk, d)
+            self.walls.append((pair_cosines(prm, ct_k, self.psi.shape),
+                               np.sqrt((g ** 2).sum(axis=0))))
+        self.cos_theta = self.walls[0][0]
 
 
 # --------------------------------------------------------------------------
@@ -185,7 +208,8 @@ def g_prime(C):
 
 def chemical_potential(prm, geo, C, L):
     """phi mu_i of eq. (2.14): bulk + gradient (L_j = div(psi grad C_j)) +
-    wetting term sum_j 3 sigma_ij sum_{q != j} cos th_jq C_j C_q |grad psi|."""
+    wetting term sum_j 3 sigma_ij sum_{q != j} cos th_jq C_j C_q |grad psi|,
+    summed over the walls (cos th^k_jq |grad psi_k|, Section 4.5)."""
     N = prm.N
     psi = geo.psi
     out = np.zeros(C.shape)
@@ -196,14 +220,17 @@ def chemical_potential(prm, geo, C, L):
                                                  - g_prime(C[i] + C[j]))
         for j in range(N):
             acc += 0.75 * prm.eps * prm.sigma[i, j] * L[j]
-        wet = np.zeros(psi.shape)
-        for j in range(N):
-            inner = np.zeros(psi.shape)
-            for q in range(N):
-                if q != j:
-                    inner += geo.cos_theta[j, q] * C[j] * C[q]
-            wet += 3.0 * prm.sigma[i, j] * inner
-        out[i] = acc + wet * geo.abs_grad_psi
+        total = np.zeros(psi.shape)
+        for cos_theta, abs_grad_psi_k in geo.walls:
+            wet = np.zeros(psi.shape)
+            for j in range(N):
+                inner = np.zeros(psi.shape)
+                for q in range(N):
+                    if q != j:
+                        inner += cos_theta[j, q] * C[j] * C[q]
+                wet += 3.0 * prm.sigma[i, j] * inner
+            total += wet * abs_grad_psi_k
+        out[i] = acc + total
     return out
 
 

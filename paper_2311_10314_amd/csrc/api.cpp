@@ -22,7 +22,8 @@ struct ddcc_ctx {
   int device = 0;
   long long n = 0;
   int Qf = 0, Qg = 0, nhist = 0, nT = 0;
-  size_t esz = 8;
+  size_t esz = 8;   // history, T and geometry fields
+  size_t pesz = 8;  // moving populations
   void* f[2] = {nullptr, nullptr};
   double* f0[2] = {nullptr, nullptr};  // rest populations, float64
   void* g[2] = {nullptr, nullptr};
@@ -30,6 +31,7 @@ struct ddcc_ctx {
   void* hist = nullptr;
   void* psi = nullptr;
   void* ct = nullptr;
+  double* work = nullptr;     // 3D: C_i and mu_i fields, 2 N n float64
   double* staging = nullptr;  // (N + dim + 1) * n float64, lazily
   double* partial = nullptr;
   int* bad = nullptr;
@@ -134,16 +136,17 @@ int validate(const ddcc_params* p, std::string& msg) {
     msg = "nz must be 1 in 2D";
     return DDCC_E_INVAL;
   }
-  if ((long long)p->nx * p->ny * p->nz > (1LL << 31)) {
-    msg = "grid larger than 2^31 nodes";
+  if ((long long)p->nx * p->ny * p->nz > (1LL << 29)) {
+    msg = "grid larger than 2^29 nodes";
     return DDCC_E_INVAL;
   }
   if (p->nphase < 2 || p->nphase > DDCC_MAX_PHASES) {
     msg = "nphase must be in [2, 4]";
     return DDCC_E_INVAL;
   }
-  if (p->precision != DDCC_FP64 && p->precision != DDCC_FP32) {
-    msg = "precision must be DDCC_FP64 or DDCC_FP32";
+  if (p->precision != DDCC_FP64 && p->precision != DDCC_FP32 &&
+      p->precision != DDCC_FP16 && p->precision != DDCC_BF16) {
+    msg = "precision must be DDCC_FP64, DDCC_FP32, DDCC_FP16 or DDCC_BF16";
     return DDCC_E_INVAL;
   }
   if (p->dim == 2 && (p->lattice_f != DDCC_D2Q9 || p->lattice_g != DDCC_D2Q9)) {
@@ -307,48 +310,40 @@ void fill_coef(const ddcc_params& p, long long n, Coef<R>& k) {
     for (int g = 0; g < 3; ++g) k.q4[j][g] = R(q4[j][g]);
 }
 
-template <class S>
-Bufs<S> bufs(ddcc_ctx* c, int mode) {
-  Bufs<S> b{};
+template <class Pop, class S>
+Bufs<Pop, S> bufs(ddcc_ctx* c, int mode) {
+  Bufs<Pop, S> b{};
   const int a = c->cur, o = c->cur ^ 1;
-  b.fA = static_cast<const S*>(c->f[a]);
+  b.fA = static_cast<const Pop*>(c->f[a]);
   b.f0A = c->f0[a];
-  b.gA = static_cast<const S*>(c->g[a]);
+  b.gA = static_cast<const Pop*>(c->g[a]);
   b.TA = static_cast<const S*>(c->T[a]);
   if (mode == MODE_INIT) {
-    b.fB = static_cast<S*>(c->f[a]);
+    b.fB = static_cast<Pop*>(c->f[a]);
     b.f0B = c->f0[a];
-    b.gB = static_cast<S*>(c->g[a]);
+    b.gB = static_cast<Pop*>(c->g[a]);
     b.TB = static_cast<S*>(c->T[a]);
   } else {
-    b.fB = static_cast<S*>(c->f[o]);
+    b.fB = static_cast<Pop*>(c->f[o]);
     b.f0B = c->f0[o];
-    b.gB = static_cast<S*>(c->g[o]);
+    b.gB = static_cast<Pop*>(c->g[o]);
     b.TB = static_cast<S*>(c->T[o]);
   }
   b.hist = static_cast<S*>(c->hist);
   b.psi = static_cast<const S*>(c->psi);
   b.ct = static_cast<const S*>(c->ct);
+  if (c->work) {
+    b.fC = c->work;
+    b.fmu = c->work + (size_t)c->p.nphase * c->n;
+  }
   return b;
 }
 
-hipError_t launch(ddcc_ctx* c, int mode, const double* inC, const double* inU,
-                  const double* inP, double* oC, double* oU, double* oP) {
-  if (c->p.precision == DDCC_FP64) {
-    Bufs<double> b = bufs<double>(c, mode);
-    b.inC = inC;
-    b.inU = inU;
-    b.inP = inP;
-    b.outC = oC;
-    b.outU = oU;
-    b.outP = oP;
-    if (c->p.dim == 2)
-      return launch_2d<double, double>(c->p.nphase, mode, c->kd, c->kd, b,
-                                       c->tile_y, c->stream);
-    return launch_3d<double, double>(c->p.nphase, mode, c->kd, c->kd, b,
-                                     c->tile_x, c->tile_y, c->stream);
-  }
-  Bufs<float> b = bufs<float>(c, mode);
+template <class Pop, class S, class R>
+hipError_t launch_as(ddcc_ctx* c, const Coef<R>& k, int mode,
+                     const double* inC, const double* inU, const double* inP,
+                     double* oC, double* oU, double* oP) {
+  Bufs<Pop, S> b = bufs<Pop, S>(c, mode);
   b.inC = inC;
   b.inU = inU;
   b.inP = inP;
@@ -356,10 +351,28 @@ hipError_t launch(ddcc_ctx* c, int mode, const double* inC, const double* inU,
   b.outU = oU;
   b.outP = oP;
   if (c->p.dim == 2)
-    return launch_2d<float, float>(c->p.nphase, mode, c->kd, c->kf, b,
-                                   c->tile_y, c->stream);
-  return launch_3d<float, float>(c->p.nphase, mode, c->kd, c->kf, b,
-                                 c->tile_x, c->tile_y, c->stream);
+    return launch_2d<Pop, S, R>(c->p.nphase, mode, c->kd, k, b, c->tile_y,
+                                c->stream);
+  return launch_3d<Pop, S, R>(c->p.nphase, mode, c->kd, k, b, c->tile_x,
+                              c->tile_y, c->stream);
+}
+
+hipError_t launch(ddcc_ctx* c, int mode, const double* inC, const double* inU,
+                  const double* inP, double* oC, double* oU, double* oP) {
+  switch (c->p.precision) {
+    case DDCC_FP64:
+      return launch_as<double, double>(c, c->kd, mode, inC, inU, inP, oC, oU,
+                                       oP);
+    case DDCC_FP16:
+      return launch_as<_Float16, float>(c, c->kf, mode, inC, inU, inP, oC, oU,
+                                        oP);
+    case DDCC_BF16:
+      return launch_as<__bf16, float>(c, c->kf, mode, inC, inU, inP, oC, oU,
+                                      oP);
+    default:
+      return launch_as<float, float>(c, c->kf, mode, inC, inU, inP, oC, oU,
+                                     oP);
+  }
 }
 
 int ensure_staging(ddcc_ctx* c) {
@@ -394,7 +407,7 @@ int upload(ddcc_ctx* c, const double* src, void* dst, size_t count) {
 void release(ddcc_ctx* c) {
   void* ptrs[] = {c->f[0],  c->f[1],   c->f0[0],    c->f0[1], c->g[0],
                   c->g[1],  c->T[0],   c->T[1],     c->hist,  c->psi,
-                  c->ct,    c->staging, c->partial, c->bad};
+                  c->ct,    c->staging, c->partial, c->bad,  c->work};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
@@ -466,6 +479,7 @@ int ddcc_create(const ddcc_params* p, void* stream, ddcc_ctx** out) {
   c->nhist = p->nphase * d + d * (d + 1) / 2 + 1;
   c->nT = d * (d - 1) / 2;
   c->esz = p->precision == DDCC_FP64 ? 8 : 4;
+  c->pesz = p->precision == DDCC_FP64 ? 8 : (p->precision == DDCC_FP32 ? 4 : 2);
   c->tile_y = d == 2 ? 8 : 4;
   c->tile_x = 64;
   if (hipGetDevice(&c->device) != hipSuccess) {
@@ -484,8 +498,8 @@ int ddcc_create(const ddcc_params* p, void* stream, ddcc_ctx** out) {
   fill_coef<double>(c->p, c->n, c->kd);
   fill_coef<float>(c->p, c->n, c->kf);
   const size_t n = (size_t)c->n;
-  const size_t sf = (size_t)p->nphase * c->Qf * n * c->esz;
-  const size_t sg = (size_t)c->Qg * n * c->esz;
+  const size_t sf = (size_t)p->nphase * c->Qf * n * c->pesz;
+  const size_t sg = (size_t)c->Qg * n * c->pesz;
   const size_t sT = (size_t)c->nT * n * c->esz;
   hipError_t e = hipSuccess;
   for (int a = 0; a < 2 && e == hipSuccess; ++a) {
@@ -499,6 +513,8 @@ int ddcc_create(const ddcc_params* p, void* stream, ddcc_ctx** out) {
   if (e == hipSuccess) e = hipMalloc(&c->psi, n * c->esz);
   if (e == hipSuccess)
     e = hipMalloc(&c->ct, (size_t)(p->nphase - 1) * n * c->esz);
+  if (e == hipSuccess && p->dim == 3)
+    e = hipMalloc(&c->work, (size_t)2 * p->nphase * n * sizeof(double));
   long long mb = (c->n + 255) / 256;
   c->mass_blocks = (int)(mb > 1024 ? 1024 : mb);
   if (e == hipSuccess)
@@ -690,16 +706,26 @@ int ddcc_mass(ddcc_ctx* c, double* mass) {
   if (!c || !mass) return fail(c, DDCC_E_INVAL, "NULL argument");
   if (!c->fields_ok) return fail(c, DDCC_E_STATE, "init_fields first");
   const int N = c->p.nphase;
-  hipError_t e =
-      c->p.precision == DDCC_FP64
-          ? launch_mass<double>(c->f0[c->cur],
-                                static_cast<const double*>(c->f[c->cur]), N,
-                                c->Qf, c->n, c->partial, c->bad,
-                                c->mass_blocks, c->stream)
-          : launch_mass<float>(c->f0[c->cur],
-                               static_cast<const float*>(c->f[c->cur]), N,
-                               c->Qf, c->n, c->partial, c->bad, c->mass_blocks,
-                               c->stream);
+  hipError_t e;
+  const void* f = c->f[c->cur];
+  const double* f0 = c->f0[c->cur];
+  switch (c->p.precision) {
+    case DDCC_FP64:
+      e = launch_mass(f0, static_cast<const double*>(f), N, c->Qf, c->n, c->n,
+                      c->partial, c->bad, c->mass_blocks, c->stream);
+      break;
+    case DDCC_FP16:
+      e = launch_mass(f0, static_cast<const _Float16*>(f), N, c->Qf, c->n, c->n,
+                      c->partial, c->bad, c->mass_blocks, c->stream);
+      break;
+    case DDCC_BF16:
+      e = launch_mass(f0, static_cast<const __bf16*>(f), N, c->Qf, c->n, c->n,
+                      c->partial, c->bad, c->mass_blocks, c->stream);
+      break;
+    default:
+      e = launch_mass(f0, static_cast<const float*>(f), N, c->Qf, c->n, c->n,
+                      c->partial, c->bad, c->mass_blocks, c->stream);
+  }
   if (e != hipSuccess) return hip_fail(c, e, "mass kernel");
   std::vector<double> part((size_t)c->mass_blocks * N);
   std::vector<int> bad(c->mass_blocks);
@@ -726,8 +752,8 @@ int ddcc_save(ddcc_ctx* c, void* buf, size_t* bytes) {
   if (!c || !bytes) return fail(c, DDCC_E_INVAL, "NULL argument");
   if (!c->fields_ok) return fail(c, DDCC_E_STATE, "init_fields first");
   const size_t n = (size_t)c->n;
-  const size_t sf = (size_t)c->p.nphase * c->Qf * n * c->esz;
-  const size_t sg = (size_t)c->Qg * n * c->esz;
+  const size_t sf = (size_t)c->p.nphase * c->Qf * n * c->pesz;
+  const size_t sg = (size_t)c->Qg * n * c->pesz;
   const size_t sh = (size_t)c->nhist * n * c->esz;
   const size_t sT = (size_t)c->nT * n * c->esz;
   const size_t s0 = (size_t)c->p.nphase * n * sizeof(double);
@@ -778,8 +804,8 @@ int ddcc_load(ddcc_ctx* c, const void* buf, size_t bytes) {
   if (!c || !buf) return fail(c, DDCC_E_INVAL, "NULL argument");
   if (!c->geom_ok) return fail(c, DDCC_E_STATE, "init_geometry first");
   const size_t n = (size_t)c->n;
-  const size_t sf = (size_t)c->p.nphase * c->Qf * n * c->esz;
-  const size_t sg = (size_t)c->Qg * n * c->esz;
+  const size_t sf = (size_t)c->p.nphase * c->Qf * n * c->pesz;
+  const size_t sg = (size_t)c->Qg * n * c->pesz;
   const size_t sh = (size_t)c->nhist * n * c->esz;
   const size_t sT = (size_t)c->nT * n * c->esz;
   const size_t s0 = (size_t)c->p.nphase * n * sizeof(double);
@@ -828,8 +854,8 @@ int ddcc_set_tile(ddcc_ctx* c, int tx, int ty) {
   if (c->p.dim == 2) {
     if (tx != 0 && tx != 64)
       return fail(c, DDCC_E_INVAL, "2D tiles are 64 nodes wide");
-    if (ty != 0 && ty != 2 && ty != 4 && ty != 8)
-      return fail(c, DDCC_E_INVAL, "2D tile height must be 2, 4 or 8");
+    if (ty != 0 && ty != 2 && ty != 4 && ty != 8 && ty != 16)
+      return fail(c, DDCC_E_INVAL, "2D tile height must be 2, 4, 8 or 16");
     if (ty) c->tile_y = ty;
   } else {
     if (tx != 0 && tx != 64)
@@ -851,6 +877,642 @@ void ddcc_destroy(ddcc_ctx* c) {
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   release(c);
   delete c;
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// Batches: many independent 2D D2Q9 boxes advanced by one launch per step.
+// ===========================================================================
+struct ddcc_batch {
+  ddcc_params p{};
+  int count = 0;
+  std::vector<int> nx, ny;
+  std::vector<long long> n, off;  // nodes and first node of each instance
+  long long ntot = 0;             // plane stride: nodes of all instances
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  size_t esz = 8, pesz = 8;
+  void* f[2] = {nullptr, nullptr};
+  double* f0[2] = {nullptr, nullptr};
+  void* g[2] = {nullptr, nullptr};
+  void* T[2] = {nullptr, nullptr};
+  void* hist = nullptr;
+  void* psi = nullptr;
+  void* ct = nullptr;
+  double* staging = nullptr;  // (N + 3) planes of ntot float64
+  double* partial = nullptr;
+  int* bad = nullptr;
+  int mass_blocks = 0;
+  BatchTile* tiles = nullptr;
+  BatchInst* insts = nullptr;
+  std::vector<unsigned> t0, t1;  // tile range of each instance
+  unsigned ntiles = 0;
+  unsigned* counters = nullptr;  // one per step of a captured graph
+  int ty = 8;
+  int blocks = 1;                // persistent workgroups per launch
+  int graph_steps = 0;           // 0: one launch per step, no graph
+  hipGraphExec_t gexec[2] = {nullptr, nullptr};  // by parity of cur
+  int cur = 0;
+  int cus = 0;
+  std::vector<char> geom_ok, fields_ok;
+  int64_t t = 0;
+  std::string err;
+  Coef<double> kd{};
+  Coef<float> kf{};
+};
+
+namespace {
+
+constexpr int kMaxGraphSteps = 1024;
+constexpr int kBatchQ = 9;
+
+int bfail(ddcc_batch* b, int code, const std::string& msg) {
+  if (b) b->err = msg;
+  return code;
+}
+
+int bhip(ddcc_batch* b, hipError_t e, const char* what) {
+  return bfail(b, e == hipErrorOutOfMemory ? DDCC_E_NOMEM : DDCC_E_HIP,
+               std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define BHIP(b, expr, what)                            \
+  do {                                                 \
+    hipError_t e_ = (expr);                            \
+    if (e_ != hipSuccess) return bhip(b, e_, what);    \
+  } while (0)
+
+int nhist_of(int N) { return 2 * N + 4; }
+
+void drop_graphs(ddcc_batch* b) {
+  for (auto& g : b->gexec)
+    if (g) {
+      (void)hipGraphExecDestroy(g);
+      g = nullptr;
+    }
+}
+
+void batch_release(ddcc_batch* b) {
+  drop_graphs(b);
+  void* ptrs[] = {b->f[0],   b->f[1], b->f0[0],    b->f0[1],    b->g[0],
+                  b->g[1],   b->T[0], b->T[1],     b->hist,     b->psi,
+                  b->ct,     b->staging, b->partial, b->bad, b->tiles,
+                  b->insts,  b->counters};
+  for (void* q : ptrs)
+    if (q) (void)hipFree(q);
+  if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
+}
+
+// Tile list for tile height ty: instances in order, tiles row-major.
+int build_tiles(ddcc_batch* b, int ty) {
+  std::vector<BatchTile> tl;
+  b->t0.assign(b->count, 0);
+  b->t1.assign(b->count, 0);
+  for (int i = 0; i < b->count; ++i) {
+    b->t0[i] = (unsigned)tl.size();
+    for (int y = 0; y < b->ny[i]; y += ty)
+      for (int x = 0; x < b->nx[i]; x += 64) tl.push_back(BatchTile{i, x, y, 0});
+    b->t1[i] = (unsigned)tl.size();
+  }
+  if (b->tiles) (void)hipFree(b->tiles);
+  b->tiles = nullptr;
+  BHIP(b, hipMalloc(&b->tiles, tl.size() * sizeof(BatchTile)), "hipMalloc tiles");
+  BHIP(b, hipMemcpyAsync(b->tiles, tl.data(), tl.size() * sizeof(BatchTile),
+                         hipMemcpyHostToDevice, b->stream),
+       "copy tiles");
+  BHIP(b, hipStreamSynchronize(b->stream), "sync");
+  b->ntiles = (unsigned)tl.size();
+  b->ty = ty;
+  // persistent launch: as many workgroups as stay resident at once
+  int per_cu = 0;
+  switch (b->p.precision) {
+    case DDCC_FP64:
+      per_cu = batch_blocks_per_cu<double, double, double>(b->p.nphase, ty);
+      break;
+    case DDCC_FP16:
+      per_cu = batch_blocks_per_cu<_Float16, float, float>(b->p.nphase, ty);
+      break;
+    case DDCC_BF16:
+      per_cu = batch_blocks_per_cu<__bf16, float, float>(b->p.nphase, ty);
+      break;
+    default:
+      per_cu = batch_blocks_per_cu<float, float, float>(b->p.nphase, ty);
+  }
+  b->blocks = (per_cu < 1 ? 1 : per_cu) * (b->cus < 1 ? 1 : b->cus);
+  drop_graphs(b);
+  return DDCC_OK;
+}
+
+template <class Pop, class S>
+Bufs<Pop, S> batch_bufs(ddcc_batch* b, int mode) {
+  Bufs<Pop, S> r{};
+  const int a = b->cur, o = b->cur ^ 1;
+  const int w = mode == MODE_INIT ? a : o;
+  r.fA = static_cast<const Pop*>(b->f[a]);
+  r.fB = static_cast<Pop*>(b->f[w]);
+  r.f0A = b->f0[a];
+  r.f0B = b->f0[w];
+  r.gA = static_cast<const Pop*>(b->g[a]);
+  r.gB = static_cast<Pop*>(b->g[w]);
+  r.TA = static_cast<const S*>(b->T[a]);
+  r.TB = static_cast<S*>(b->T[w]);
+  r.hist = static_cast<S*>(b->hist);
+  r.psi = static_cast<const S*>(b->psi);
+  r.ct = static_cast<const S*>(b->ct);
+  return r;
+}
+
+template <class Pop, class S, class R>
+hipError_t batch_launch_as(ddcc_batch* b, const Coef<R>& k, int mode,
+                           unsigned t0, unsigned nt, unsigned* counter,
+                           const double* inC, const double* inU,
+                           const double* inP, double* oC, double* oU,
+                           double* oP) {
+  Bufs<Pop, S> r = batch_bufs<Pop, S>(b, mode);
+  r.inC = inC;
+  r.inU = inU;
+  r.inP = inP;
+  r.outC = oC;
+  r.outU = oU;
+  r.outP = oP;
+  long long nb = b->blocks;
+  if (nb > nt) nb = nt;
+  if (nb < 1) nb = 1;
+  return launch_2d_batch<Pop, S, R>(b->p.nphase, mode, b->kd, k, r,
+                                    b->tiles + t0, b->insts, nt, counter,
+                                    (int)nb, b->ty, b->stream);
+}
+
+// Zero *counter, then run `mode` over tiles [t0, t0 + nt).
+hipError_t batch_launch(ddcc_batch* b, int mode, unsigned t0, unsigned nt,
+                        unsigned* counter, const double* inC = nullptr,
+                        const double* inU = nullptr, const double* inP = nullptr,
+                        double* oC = nullptr, double* oU = nullptr,
+                        double* oP = nullptr) {
+  hipError_t e = launch_fill_u32(counter, 0u, 1, b->stream);
+  if (e != hipSuccess) return e;
+  switch (b->p.precision) {
+    case DDCC_FP64:
+      return batch_launch_as<double, double>(b, b->kd, mode, t0, nt, counter,
+                                             inC, inU, inP, oC, oU, oP);
+    case DDCC_FP16:
+      return batch_launch_as<_Float16, float>(b, b->kf, mode, t0, nt, counter,
+                                              inC, inU, inP, oC, oU, oP);
+    case DDCC_BF16:
+      return batch_launch_as<__bf16, float>(b, b->kf, mode, t0, nt, counter,
+                                            inC, inU, inP, oC, oU, oP);
+    default:
+      return batch_launch_as<float, float>(b, b->kf, mode, t0, nt, counter,
+                                           inC, inU, inP, oC, oU, oP);
+  }
+}
+
+// Copies instance i's planes [0, planes) between a host array laid out
+// [plane][n_i] and batch-layout device memory [plane][ntot] at off_i.
+int copy_planes(ddcc_batch* b, int i, void* dev, const void* host, int planes,
+                size_t esz, hipMemcpyKind kind) {
+  for (int q = 0; q < planes; ++q) {
+    char* d = static_cast<char*>(dev) + ((size_t)q * b->ntot + b->off[i]) * esz;
+    const char* h = static_cast<const char*>(host) + (size_t)q * b->n[i] * esz;
+    hipError_t e = kind == hipMemcpyHostToDevice
+                       ? hipMemcpyAsync(d, h, b->n[i] * esz, kind, b->stream)
+                       : hipMemcpyAsync(const_cast<char*>(h), d, b->n[i] * esz,
+                                        kind, b->stream);
+    if (e != hipSuccess) return bhip(b, e, "plane copy");
+  }
+  return DDCC_OK;
+}
+
+int batch_check(ddcc_batch* b, int i) {
+  if (!b) return DDCC_E_INVAL;
+  if (i < 0 || i >= b->count) return bfail(b, DDCC_E_INVAL, "instance out of range");
+  return DDCC_OK;
+}
+
+// One step of every instance; graph replays use counters [0, graph_steps).
+int batch_step_direct(ddcc_batch* b) {
+  hipError_t e = batch_launch(b, MODE_STEP, 0, b->ntiles, b->counters);
+  if (e != hipSuccess) return bhip(b, e, "batch step kernel");
+  b->cur ^= 1;
+  ++b->t;
+  return DDCC_OK;
+}
+
+int batch_capture(ddcc_batch* b) {
+  const int par = b->cur;
+  hipGraph_t graph = nullptr;
+  BHIP(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal),
+       "begin capture");
+  hipError_t e = launch_fill_u32(b->counters, 0u, b->graph_steps, b->stream);
+  for (int s = 0; s < b->graph_steps && e == hipSuccess; ++s) {
+    switch (b->p.precision) {
+      case DDCC_FP64:
+        e = batch_launch_as<double, double>(b, b->kd, MODE_STEP, 0, b->ntiles,
+                                            b->counters + s, nullptr, nullptr,
+                                            nullptr, nullptr, nullptr, nullptr);
+        break;
+      case DDCC_FP16:
+        e = batch_launch_as<_Float16, float>(b, b->kf, MODE_STEP, 0, b->ntiles,
+                                             b->counters + s, nullptr, nullptr,
+                                             nullptr, nullptr, nullptr, nullptr);
+        break;
+      case DDCC_BF16:
+        e = batch_launch_as<__bf16, float>(b, b->kf, MODE_STEP, 0, b->ntiles,
+                                           b->counters + s, nullptr, nullptr,
+                                           nullptr, nullptr, nullptr, nullptr);
+        break;
+      default:
+        e = batch_launch_as<float, float>(b, b->kf, MODE_STEP, 0, b->ntiles,
+                                          b->counters + s, nullptr, nullptr,
+                                          nullptr, nullptr, nullptr, nullptr);
+    }
+    b->cur ^= 1;
+  }
+  b->cur = par;
+  hipError_t e2 = hipStreamEndCapture(b->stream, &graph);
+  if (e != hipSuccess || e2 != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return bhip(b, e != hipSuccess ? e : e2, "graph capture");
+  }
+  e = hipGraphInstantiate(&b->gexec[par], graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) {
+    b->gexec[par] = nullptr;
+    return bhip(b, e, "graph instantiate");
+  }
+  return DDCC_OK;
+}
+
+template <class S>
+int upload_fields(ddcc_batch* b, int i, const double* src, void* dst,
+                  int planes) {
+  std::vector<S> tmp((size_t)planes * b->n[i]);
+  for (size_t k = 0; k < tmp.size(); ++k) tmp[k] = S(src[k]);
+  int rc = copy_planes(b, i, dst, tmp.data(), planes, sizeof(S),
+                       hipMemcpyHostToDevice);
+  if (rc) return rc;
+  BHIP(b, hipStreamSynchronize(b->stream), "sync");
+  return DDCC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ddcc_batch_create(const ddcc_params* p, int count, const int* nx,
+                      const int* ny, void* stream, ddcc_batch** out) {
+  if (!out) return DDCC_E_INVAL;
+  *out = nullptr;
+  if (!p || !nx || !ny || count < 1) return DDCC_E_INVAL;
+  if (p->dim != 2) return DDCC_E_UNSUPPORTED;
+  long long ntot = 0;
+  for (int i = 0; i < count; ++i) {
+    if (nx[i] < 1 || ny[i] < 1) return DDCC_E_INVAL;
+    ntot += (long long)nx[i] * ny[i];
+  }
+  if (ntot > (1LL << 29)) return DDCC_E_INVAL;
+  ddcc_params q = *p;
+  q.nx = nx[0];
+  q.ny = ny[0];
+  q.nz = 1;
+  std::string msg;
+  int rc = validate(&q, msg);
+  if (rc != DDCC_OK) return rc;
+  ddcc_batch* b = new (std::nothrow) ddcc_batch();
+  if (!b) return DDCC_E_NOMEM;
+  b->p = q;
+  b->count = count;
+  b->nx.assign(nx, nx + count);
+  b->ny.assign(ny, ny + count);
+  for (int i = 0; i < count; ++i) {
+    b->n.push_back((long long)nx[i] * ny[i]);
+    b->off.push_back(b->ntot);
+    b->ntot += b->n.back();
+  }
+  b->geom_ok.assign(count, 0);
+  b->fields_ok.assign(count, 0);
+  b->esz = q.precision == DDCC_FP64 ? 8 : 4;
+  b->pesz = q.precision == DDCC_FP64 ? 8 : (q.precision == DDCC_FP32 ? 4 : 2);
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&b->cus, hipDeviceAttributeMultiprocessorCount,
+                            dev) != hipSuccess) {
+    delete b;
+    return DDCC_E_HIP;
+  }
+  // A captured graph cannot use the legacy default stream.
+  if (stream) {
+    b->stream = static_cast<hipStream_t>(stream);
+  } else {
+    if (hipStreamCreate(&b->stream) != hipSuccess) {
+      delete b;
+      return DDCC_E_HIP;
+    }
+    b->own_stream = true;
+  }
+  // kernel constants: plane stride ntot; the box sizes come per instance
+  ddcc_params qs = q;
+  fill_coef<double>(qs, b->ntot, b->kd);
+  fill_coef<float>(qs, b->ntot, b->kf);
+  const int N = q.nphase;
+  const size_t nt = (size_t)b->ntot;
+  hipError_t e = hipSuccess;
+  for (int a = 0; a < 2 && e == hipSuccess; ++a) {
+    e = hipMalloc(&b->f[a], (size_t)N * kBatchQ * nt * b->pesz);
+    if (e == hipSuccess) e = hipMalloc(&b->f0[a], (size_t)N * nt * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc(&b->g[a], (size_t)kBatchQ * nt * b->pesz);
+    if (e == hipSuccess) e = hipMalloc(&b->T[a], nt * b->esz);
+  }
+  if (e == hipSuccess) e = hipMalloc(&b->hist, (size_t)nhist_of(N) * nt * b->esz);
+  if (e == hipSuccess) e = hipMalloc(&b->psi, nt * b->esz);
+  if (e == hipSuccess) e = hipMalloc(&b->ct, (size_t)(N - 1) * nt * b->esz);
+  if (e == hipSuccess)
+    e = hipMalloc(&b->staging, (size_t)(N + 3) * nt * sizeof(double));
+  long long mb = (ntot + 255) / 256;
+  b->mass_blocks = (int)(mb > 1024 ? 1024 : mb);
+  if (e == hipSuccess)
+    e = hipMalloc(&b->partial, (size_t)b->mass_blocks * N * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc(&b->bad, (size_t)b->mass_blocks * sizeof(int));
+  if (e == hipSuccess) e = hipMalloc(&b->counters, kMaxGraphSteps * sizeof(unsigned));
+  if (e == hipSuccess) {
+    std::vector<BatchInst> ins(count);
+    for (int i = 0; i < count; ++i) ins[i] = BatchInst{nx[i], ny[i], b->n[i], b->off[i]};
+    e = hipMalloc(&b->insts, count * sizeof(BatchInst));
+    if (e == hipSuccess)
+      e = hipMemcpy(b->insts, ins.data(), count * sizeof(BatchInst),
+                    hipMemcpyHostToDevice);
+  }
+  if (e != hipSuccess || build_tiles(b, 8) != DDCC_OK) {
+    batch_release(b);
+    delete b;
+    return e == hipErrorOutOfMemory ? DDCC_E_NOMEM : DDCC_E_HIP;
+  }
+  *out = b;
+  return DDCC_OK;
+}
+
+int ddcc_batch_init_geometry(ddcc_batch* b, int i, const double* psi,
+                             const double* ct) {
+  int rc = batch_check(b, i);
+  if (rc) return rc;
+  if (!psi) return bfail(b, DDCC_E_INVAL, "psi is NULL");
+  const size_t n = (size_t)b->n[i];
+  const int N = b->p.nphase;
+  for (size_t k = 0; k < n; ++k)
+    if (!(psi[k] >= 0.0 && psi[k] <= 1.0))
+      return bfail(b, DDCC_E_INVAL, "psi outside [0, 1]");
+  std::vector<double> zeros;
+  if (ct) {
+    for (size_t k = 0; k < (size_t)(N - 1) * n; ++k)
+      if (!(ct[k] >= -1.0 && ct[k] <= 1.0))
+        return bfail(b, DDCC_E_INVAL, "cos theta outside [-1, 1]");
+  } else {
+    zeros.assign((size_t)(N - 1) * n, 0.0);
+    ct = zeros.data();
+  }
+  const bool f64 = b->p.precision == DDCC_FP64;
+  rc = f64 ? upload_fields<double>(b, i, psi, b->psi, 1)
+           : upload_fields<float>(b, i, psi, b->psi, 1);
+  if (rc) return rc;
+  rc = f64 ? upload_fields<double>(b, i, ct, b->ct, N - 1)
+           : upload_fields<float>(b, i, ct, b->ct, N - 1);
+  if (rc) return rc;
+  b->geom_ok[i] = 1;
+  b->fields_ok[i] = 0;
+  return DDCC_OK;
+}
+
+int ddcc_batch_init_fields(ddcc_batch* b, int i, const double* C,
+                           const double* u, const double* P) {
+  int rc = batch_check(b, i);
+  if (rc) return rc;
+  if (!b->geom_ok[i]) return bfail(b, DDCC_E_STATE, "init_geometry first");
+  if (!C) return bfail(b, DDCC_E_INVAL, "C is NULL");
+  const int N = b->p.nphase;
+  const size_t n = (size_t)b->n[i];
+  if (!all_finite(C, N * n) || (u && !all_finite(u, 2 * n)) ||
+      (P && !all_finite(P, n)))
+    return bfail(b, DDCC_E_INVAL, "non-finite initial field");
+  double* sC = b->staging;
+  double* sU = sC + (size_t)N * b->ntot;
+  double* sP = sU + 2 * (size_t)b->ntot;
+  rc = copy_planes(b, i, sC, C, N, sizeof(double), hipMemcpyHostToDevice);
+  if (!rc && u) rc = copy_planes(b, i, sU, u, 2, sizeof(double), hipMemcpyHostToDevice);
+  if (!rc && P) rc = copy_planes(b, i, sP, P, 1, sizeof(double), hipMemcpyHostToDevice);
+  if (rc) return rc;
+  // initialisation writes the populations of the current level in place
+  hipError_t e = batch_launch(b, MODE_INIT, b->t0[i], b->t1[i] - b->t0[i],
+                              b->counters, sC, u ? sU : nullptr,
+                              P ? sP : nullptr);
+  if (e != hipSuccess) return bhip(b, e, "batch init kernel");
+  BHIP(b, hipStreamSynchronize(b->stream), "sync");
+  b->fields_ok[i] = 1;
+  return DDCC_OK;
+}
+
+int ddcc_batch_step(ddcc_batch* b, int64_t nsteps) {
+  if (!b) return DDCC_E_INVAL;
+  if (nsteps < 0) return bfail(b, DDCC_E_INVAL, "nsteps < 0");
+  for (int i = 0; i < b->count; ++i)
+    if (!b->fields_ok[i])
+      return bfail(b, DDCC_E_STATE, "every instance needs init_fields first");
+  int64_t left = nsteps;
+  if (b->graph_steps > 0) {
+    while (left >= b->graph_steps) {
+      if (!b->gexec[b->cur]) {
+        int rc = batch_capture(b);
+        if (rc) return rc;
+      }
+      BHIP(b, hipGraphLaunch(b->gexec[b->cur], b->stream), "graph launch");
+      // an even number of steps leaves the level parity unchanged
+      b->t += b->graph_steps;
+      left -= b->graph_steps;
+    }
+  }
+  for (; left > 0; --left) {
+    int rc = batch_step_direct(b);
+    if (rc) return rc;
+  }
+  return DDCC_OK;
+}
+
+int ddcc_batch_read_moments(ddcc_batch* b, int i, double* C, double* u,
+                            double* P) {
+  int rc = batch_check(b, i);
+  if (rc) return rc;
+  if (!b->fields_ok[i]) return bfail(b, DDCC_E_STATE, "init_fields first");
+  const int N = b->p.nphase;
+  double* sC = b->staging;
+  double* sU = sC + (size_t)N * b->ntot;
+  double* sP = sU + 2 * (size_t)b->ntot;
+  hipError_t e = batch_launch(b, MODE_MOMENTS, b->t0[i], b->t1[i] - b->t0[i],
+                              b->counters, nullptr, nullptr, nullptr, sC, sU,
+                              sP);
+  if (e != hipSuccess) return bhip(b, e, "batch moments kernel");
+  if (C) rc = copy_planes(b, i, sC, C, N, sizeof(double), hipMemcpyDeviceToHost);
+  if (!rc && u) rc = copy_planes(b, i, sU, u, 2, sizeof(double), hipMemcpyDeviceToHost);
+  if (!rc && P) rc = copy_planes(b, i, sP, P, 1, sizeof(double), hipMemcpyDeviceToHost);
+  if (rc) return rc;
+  BHIP(b, hipStreamSynchronize(b->stream), "sync");
+  return DDCC_OK;
+}
+
+int ddcc_batch_mass(ddcc_batch* b, int i, double* mass) {
+  int rc = batch_check(b, i);
+  if (rc) return rc;
+  if (!mass) return bfail(b, DDCC_E_INVAL, "mass is NULL");
+  if (!b->fields_ok[i]) return bfail(b, DDCC_E_STATE, "init_fields first");
+  const int N = b->p.nphase;
+  const long long o = b->off[i];
+  const double* f0 = b->f0[b->cur] + o;
+  hipError_t e;
+  switch (b->p.precision) {
+    case DDCC_FP64:
+      e = launch_mass(f0, static_cast<const double*>(b->f[b->cur]) + o, N,
+                      kBatchQ, b->n[i], b->ntot, b->partial, b->bad,
+                      b->mass_blocks, b->stream);
+      break;
+    case DDCC_FP16:
+      e = launch_mass(f0, static_cast<const _Float16*>(b->f[b->cur]) + o, N,
+                      kBatchQ, b->n[i], b->ntot, b->partial, b->bad,
+                      b->mass_blocks, b->stream);
+      break;
+    case DDCC_BF16:
+      e = launch_mass(f0, static_cast<const __bf16*>(b->f[b->cur]) + o, N,
+                      kBatchQ, b->n[i], b->ntot, b->partial, b->bad,
+                      b->mass_blocks, b->stream);
+      break;
+    default:
+      e = launch_mass(f0, static_cast<const float*>(b->f[b->cur]) + o, N,
+                      kBatchQ, b->n[i], b->ntot, b->partial, b->bad,
+                      b->mass_blocks, b->stream);
+  }
+  if (e != hipSuccess) return bhip(b, e, "mass kernel");
+  std::vector<double> part((size_t)b->mass_blocks * N);
+  std::vector<int> bad(b->mass_blocks);
+  BHIP(b, hipMemcpyAsync(part.data(), b->partial, part.size() * sizeof(double),
+                         hipMemcpyDeviceToHost, b->stream),
+       "copy partials");
+  BHIP(b, hipMemcpyAsync(bad.data(), b->bad, bad.size() * sizeof(int),
+                         hipMemcpyDeviceToHost, b->stream),
+       "copy flags");
+  BHIP(b, hipStreamSynchronize(b->stream), "sync");
+  for (int k = 0; k < N; ++k) {
+    double s = 0.0;
+    for (int q = 0; q < b->mass_blocks; ++q) s += part[(size_t)q * N + k];
+    mass[k] = s;
+  }
+  for (int q = 0; q < b->mass_blocks; ++q)
+    if (bad[q]) return bfail(b, DDCC_E_NONFINITE, "non-finite population");
+  return DDCC_OK;
+}
+
+int ddcc_batch_set_tile(ddcc_batch* b, int ty) {
+  if (!b) return DDCC_E_INVAL;
+  if (ty != 4 && ty != 8 && ty != 16)
+    return bfail(b, DDCC_E_INVAL, "batch tile height must be 4, 8 or 16");
+  return build_tiles(b, ty);
+}
+
+int ddcc_batch_set_graph(ddcc_batch* b, int steps_per_graph) {
+  if (!b) return DDCC_E_INVAL;
+  if (steps_per_graph < 0 || steps_per_graph > kMaxGraphSteps ||
+      steps_per_graph % 2 != 0)
+    return bfail(b, DDCC_E_INVAL,
+                 "steps per graph must be even and in [0, 1024]");
+  drop_graphs(b);
+  b->graph_steps = steps_per_graph;
+  return DDCC_OK;
+}
+
+int ddcc_batch_autotune(ddcc_batch* b, int steps, int* ty_out) {
+  if (!b) return DDCC_E_INVAL;
+  if (steps < 1) return bfail(b, DDCC_E_INVAL, "steps < 1");
+  for (int i = 0; i < b->count; ++i)
+    if (!b->fields_ok[i])
+      return bfail(b, DDCC_E_STATE, "every instance needs init_fields first");
+  // The trial steps change the state: keep a copy of the current level.
+  const int N = b->p.nphase;
+  const size_t nt = (size_t)b->ntot;
+  const size_t sizes[5] = {(size_t)N * kBatchQ * nt * b->pesz,
+                           (size_t)N * nt * sizeof(double),
+                           (size_t)kBatchQ * nt * b->pesz, nt * b->esz,
+                           (size_t)nhist_of(N) * nt * b->esz};
+  const int cur0 = b->cur;
+  void* src[5] = {b->f[cur0], b->f0[cur0], b->g[cur0], b->T[cur0], b->hist};
+  void* keep[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  hipError_t e = hipSuccess;
+  for (int q = 0; q < 5 && e == hipSuccess; ++q) {
+    e = hipMalloc(&keep[q], sizes[q]);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(keep[q], src[q], sizes[q], hipMemcpyDeviceToDevice,
+                         b->stream);
+  }
+  const int cands[3] = {4, 8, 16};
+  float best_ms = 0;
+  int best = b->ty;
+  hipEvent_t t0 = nullptr, t1 = nullptr;
+  if (e == hipSuccess) e = hipEventCreate(&t0);
+  if (e == hipSuccess) e = hipEventCreate(&t1);
+  const int64_t tsave = b->t;
+  for (int c = 0; c < 3 && e == hipSuccess; ++c) {
+    if (build_tiles(b, cands[c]) != DDCC_OK) {
+      e = hipErrorUnknown;
+      break;
+    }
+    for (int w = 0; w < 2 && e == hipSuccess; ++w)
+      if (batch_step_direct(b) != DDCC_OK) e = hipErrorUnknown;
+    if (e == hipSuccess) e = hipEventRecord(t0, b->stream);
+    for (int s = 0; s < steps && e == hipSuccess; ++s)
+      if (batch_step_direct(b) != DDCC_OK) e = hipErrorUnknown;
+    if (e == hipSuccess) e = hipEventRecord(t1, b->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(t1);
+    float ms = 0;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
+    if (e == hipSuccess && (c == 0 || ms < best_ms)) {
+      best_ms = ms;
+      best = cands[c];
+    }
+  }
+  // restore the level the trials started from
+  b->cur = cur0;
+  b->t = tsave;
+  for (int q = 0; q < 5; ++q)
+    if (keep[q]) {
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(src[q], keep[q], sizes[q], hipMemcpyDeviceToDevice,
+                           b->stream);
+    }
+  if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+  for (int q = 0; q < 5; ++q)
+    if (keep[q]) (void)hipFree(keep[q]);
+  if (t0) (void)hipEventDestroy(t0);
+  if (t1) (void)hipEventDestroy(t1);
+  if (e != hipSuccess) return bhip(b, e, "autotune");
+  int rc = build_tiles(b, best);
+  if (rc) return rc;
+  if (ty_out) *ty_out = best;
+  return DDCC_OK;
+}
+
+int ddcc_batch_sync(ddcc_batch* b) {
+  if (!b) return DDCC_E_INVAL;
+  BHIP(b, hipStreamSynchronize(b->stream), "sync");
+  return DDCC_OK;
+}
+
+int64_t ddcc_batch_time(const ddcc_batch* b) { return b ? b->t : -1; }
+
+const char* ddcc_batch_last_error(const ddcc_batch* b) {
+  return b ? b->err.c_str() : "NULL batch";
+}
+
+void ddcc_batch_destroy(ddcc_batch* b) {
+  if (!b) return;
+  if (b->stream) (void)hipStreamSynchronize(b->stream);
+  batch_release(b);
+  delete b;
 }
 
 }  // extern "C"

@@ -11,7 +11,8 @@ constexpr int kMaxN = 4;
 template <class R>
 struct Coef {
   int nx, ny, nz;
-  long long n;          // nodes
+  long long n;          // nodes (plane stride)
+  static constexpr unsigned off = 0;  // first node of the box in each plane
   R cs2, inv_cs2;       // c_s^2 = d0 (c = 1)
   R psi_min, lam, rho0;
   R m0;

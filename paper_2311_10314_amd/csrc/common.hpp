@@ -11,15 +11,28 @@ __device__ inline R gprime(R C) {
   return R(2) * C * (C - R(1)) * (R(2) * C - R(1));
 }
 
-// Periodic wrap of an index that may lie several periods outside [0, n).
+// Periodic wrap of an index into [0, n). Halo indices lie within one period
+// of the grid unless the grid is narrower than a tile; those take the
+// (slow) integer remainder.
 __device__ inline int wrap(int v, int n) {
-  int m = v % n;
+  if (v >= -n && v < 2 * n) return v < 0 ? v + n : (v >= n ? v - n : v);
+  const int m = v % n;
   return m < 0 ? m + n : m;
 }
 
-template <class S, class R>
-__device__ inline R ld(const S* p) {
-  return static_cast<R>(*p);
+// Element i of a plane: the byte offset is formed in 32 bits, so that the
+// plane pointer stays in scalar registers and each access is one global
+// load/store with a 32-bit vector offset (planes are at most 4 GiB; the
+// library limits grids to 2^29 nodes).
+template <class T>
+__device__ inline T ldp(const T* plane, unsigned i) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(plane) +
+                                     i * unsigned(sizeof(T)));
+}
+
+template <class T>
+__device__ inline void stp(T* plane, unsigned i, T v) {
+  *reinterpret_cast<T*>(reinterpret_cast<char*>(plane) + i * unsigned(sizeof(T))) = v;
 }
 
 }  // namespace ddcc

@@ -13,14 +13,16 @@ enum { MODE_STEP = 0, MODE_INIT = 1, MODE_MOMENTS = 2 };
 //   fA/gA/TA: current level (read), fB/gB/TB: next level (written);
 //   in MODE_INIT the kernels write fB/gB/TB and read inC/inU/inP;
 //   in MODE_MOMENTS they write outC/outU/outP and nothing else.
-template <class S>
+// Pop is the storage type of the moving populations (f^i_p, p >= 1, and
+// g_p); S that of the history, T and geometry fields.
+template <class Pop, class S>
 struct Bufs {
-  const S* fA;     // phase populations [N][Q][n]; plane p = 0 unused
-  S* fB;
+  const Pop* fA;   // phase populations [N][Q][n]; plane p = 0 unused
+  Pop* fB;
   const double* f0A;  // rest populations of the phase sets [N][n], float64
   double* f0B;
-  const S* gA;
-  S* gB;
+  const Pop* gA;
+  Pop* gB;
   S* hist;
   const S* TA;
   S* TB;
@@ -32,27 +34,70 @@ struct Bufs {
   double* outC;
   double* outU;
   double* outP;
+  double* fC;      // 3D work fields: C_i [N][n] and mu_i [N][n], float64
+  double* fmu;
 };
+
+// A population value v written in a narrower storage type: returns the
+// stored value and adds the rounding v - stored to comp, so that the float64
+// rest population can take it back and the phase mass stays exact.
+template <class Pop, class R>
+__device__ inline Pop narrow(R v, double& comp) {
+  const Pop s = Pop(v);
+  if constexpr (sizeof(Pop) < sizeof(R)) comp += double(v) - double(R(s));
+  return s;
+}
 
 // kd: the float64 constants (fields C, mu, psi, rest populations);
 // k: the same constants in the collision arithmetic type R.
-template <class S, class R>
+template <class Pop, class S, class R>
 hipError_t launch_2d(int nphase, int mode, const Coef<double>& kd,
-                     const Coef<R>& k, const Bufs<S>& b, int ty,
+                     const Coef<R>& k, const Bufs<Pop, S>& b, int ty,
                      hipStream_t st);
 
-template <class S, class R>
+template <class Pop, class S, class R>
 hipError_t launch_3d(int nphase, int mode, const Coef<double>& kd,
-                     const Coef<R>& k, const Bufs<S>& b, int tx, int ty,
+                     const Coef<R>& k, const Bufs<Pop, S>& b, int tx, int ty,
                      hipStream_t st);
 
-// Per-phase sums of all populations (rest plane f0 [N][n] plus planes
-// p >= 1 of f [N][Q][n]) into partial[block * N + i], plus a non-finite flag
-// per block in bad[block].
-template <class S>
-hipError_t launch_mass(const double* f0, const S* f, int nphase, int Q,
-                       long long n, double* partial, int* bad, int nblocks,
-                       hipStream_t st);
+// Batches of independent 2D boxes: one work-queue entry per tile, and the
+// size and node offset of every instance. Each plane of each buffer holds
+// every instance, instance i at nodes [off_i, off_i + n_i); the plane stride
+// is the total node count (the n of the Coef handed to the batch kernel).
+struct BatchTile {
+  int inst, x0, y0, pad;
+};
+struct BatchInst {
+  int nx, ny;
+  long long n, off;
+};
+
+// One step (or initialisation, or moment read-out) of the instances whose
+// tiles are listed: a persistent launch of nblocks workgroups that drain the
+// tile queue; *counter must be zero at launch.
+template <class Pop, class S, class R>
+hipError_t launch_2d_batch(int nphase, int mode, const Coef<double>& kd,
+                           const Coef<R>& k,
+                           const Bufs<Pop, S>& b, const BatchTile* tiles,
+                           const BatchInst* insts, unsigned ntiles,
+                           unsigned* counter, int nblocks, int ty,
+                           hipStream_t st);
+
+// Resident workgroups per compute unit of the batch kernel (0 on error).
+template <class Pop, class S, class R>
+int batch_blocks_per_cu(int nphase, int ty);
+
+// dst[i] = v for i < count (a kernel, so that it can sit in a captured graph).
+hipError_t launch_fill_u32(unsigned* dst, unsigned v, long long count,
+                           hipStream_t st);
+
+// Per-phase sums of all populations (rest plane f0 [N][stride_n] plus
+// planes p >= 1 of f [N][Q][stride_n], nodes [0, n) of each plane) into
+// partial[block * N + i], plus a non-finite flag per block in bad[block].
+template <class Pop>
+hipError_t launch_mass(const double* f0, const Pop* f, int nphase, int Q,
+                       long long n, long long stride_n, double* partial,
+                       int* bad, int nblocks, hipStream_t st);
 
 // dst[i] = S(src[i]) for i < count.
 template <class S>

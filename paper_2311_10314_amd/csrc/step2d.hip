@@ -85,18 +85,31 @@ __device__ inline Patch<R> patch(const R (&a)[H][W], int x, int y) {
   return p;
 }
 
+// Box a tile belongs to: nx x ny nodes starting at node `off` of planes of
+// n nodes (one box: off = 0, n = nx ny; an instance of a batch: its offset in
+// planes that hold every instance). The single-box kernel passes its Coef for
+// the halo stages (same members nx, ny, n and off = 0), so the sizes stay
+// kernel arguments there.
+struct Grid {
+  int nx, ny;
+  long long n;
+  unsigned off;
+};
+
 // Pull: population p at (gx, gy) comes from (gx - c_px, gy - c_py).
 struct Nbr {
   int xm, xp, ym, yp, x, y, nx;
+  unsigned off;
   __device__ inline unsigned src(int cx, int cy) const {
     const int sx = cx == 1 ? xm : (cx == -1 ? xp : x);
     const int sy = cy == 1 ? ym : (cy == -1 ? yp : y);
-    return unsigned(sy * nx + sx);
+    return off + unsigned(sy * nx + sx);
   }
 };
 
-__device__ inline Nbr make_nbr(int gx, int gy, int nx, int ny) {
+__device__ inline Nbr make_nbr(int gx, int gy, int nx, int ny, unsigned off) {
   Nbr b;
+  b.off = off;
   b.x = gx;
   b.y = gy;
   b.nx = nx;
@@ -107,7 +120,7 @@ __device__ inline Nbr make_nbr(int gx, int gy, int nx, int ny) {
   return b;
 }
 
-template <int N, class S, class R, int MODE, int TY>
+template <int N, class Pop, class S, class R, int MODE, int TY>
 struct Step2D {
   using D = double;
   static constexpr int Q = 9;
@@ -156,30 +169,32 @@ struct Step2D {
   }
 
   // Phase 1 at C-region coordinates (lx, ly).
+  template <class G>
   __device__ static inline void node1(Smem& sm, const Coef<D>& k,
-                                      const Bufs<S>& b, int x0, int y0, int lx,
+                                      const Bufs<Pop, S>& b, const G& gd, int x0,
+                                      int y0, int lx,
                                       int ly, D* psiC_out) {
-    const int gx = wrap(x0 + lx - 2, k.nx), gy = wrap(y0 + ly - 2, k.ny);
-    const unsigned idx = unsigned(gy * k.nx + gx);
-    const D psi = ld<S, D>(&b.psi[idx]);
+    const int gx = wrap(x0 + lx - 2, gd.nx), gy = wrap(y0 + ly - 2, gd.ny);
+    const unsigned idx = gd.off + unsigned(gy * gd.nx + gx);
+    const D psi = D(ldp(b.psi, idx));
     D rho = D(0);
     if constexpr (MODE == MODE_INIT) {
 #pragma unroll
-      for (int i = 0; i < N; ++i) psiC_out[i] = psi * (b.inC + (long long)(i) * k.n)[idx];
+      for (int i = 0; i < N; ++i) psiC_out[i] = psi * ldp(b.inC + (long long)(i) * gd.n, idx);
     } else {
-      const Nbr nb = make_nbr(gx, gy, k.nx, k.ny);
+      const Nbr nb = make_nbr(gx, gy, gd.nx, gd.ny, gd.off);
 #pragma unroll
       for (int i = 0; i < N; ++i) {
         // phi C_i = sum_p f^i_p (Section 3); the rest population does not
         // move and lives in the float64 plane
-        const S* f = b.fA + (long long)i * Q * k.n;
+        const Pop* f = b.fA + (long long)i * Q * gd.n;
         // moving populations summed in the storage precision, the float64
         // rest population added last
         R mv = R(0);
 #pragma unroll
         for (int p = 1; p < Q; ++p)
-          mv += ld<S, R>(&(f + (long long)(p) * k.n)[nb.src(D2Q9::c[p].x, D2Q9::c[p].y)]);
-        psiC_out[i] = (b.f0A + (long long)(i) * k.n)[idx] + D(mv);
+          mv += R(ldp(f + (long long)(p) * gd.n, nb.src(D2Q9::c[p].x, D2Q9::c[p].y)));
+        psiC_out[i] = ldp(b.f0A + (long long)(i) * gd.n, idx) + D(mv);
       }
     }
     // C_i = phi C_i / sum_j phi C_j: equal to phi C_i / phi while the
@@ -199,12 +214,14 @@ struct Step2D {
   }
 
   // Phase 2 at mu-region coordinates (mx, my): phi mu_i (eq. 2.14).
+  template <class G>
   __device__ static inline void node2(Smem& sm, const Coef<D>& k,
-                                      const Bufs<S>& b, int x0, int y0, int mx,
+                                      const Bufs<Pop, S>& b, const G& gd, int x0,
+                                      int y0, int mx,
                                       int my, D* psimu_out) {
     const int lx = mx + 1, ly = my + 1;
-    const int gx = wrap(x0 + mx - 1, k.nx), gy = wrap(y0 + my - 1, k.ny);
-    const unsigned idx = unsigned(gy * k.nx + gx);
+    const int gx = wrap(x0 + mx - 1, gd.nx), gy = wrap(y0 + my - 1, gd.ny);
+    const unsigned idx = gd.off + unsigned(gy * gd.nx + gx);
     const Patch<D> ps = patch(sm.psi, lx, ly);
     const D psi = ps.v[1][1];
     const D psih = psi > k.psi_min ? psi : k.psi_min;
@@ -220,7 +237,7 @@ struct Step2D {
     // cos theta_jq from the N-1 stored cos theta_iN (eq. 2.9)
     D ct[N];
 #pragma unroll
-    for (int i = 0; i < N - 1; ++i) ct[i] = ld<S, D>(&(b.ct + (long long)(i) * k.n)[idx]);
+    for (int i = 0; i < N - 1; ++i) ct[i] = D(ldp(b.ct + (long long)(i) * gd.n, idx));
     ct[N - 1] = D(0);
     D W[N];  // sum_{q != j} cos theta_jq C_j C_q
 #pragma unroll
@@ -250,39 +267,79 @@ struct Step2D {
       psimu_out[i] = pm;
       sm.mu[i][my][mx] = pm / psih;
     }
-    if constexpr (MODE != MODE_INIT) sm.T[my][mx] = ld<S, R>(&b.TA[idx]);
+    if constexpr (MODE != MODE_INIT) sm.T[my][mx] = R(ldp(b.TA, idx));
   }
 
   __device__ static void run(const Coef<D>& kd, const Coef<R>& k,
-                             const Bufs<S>& b) {
+                             const Bufs<Pop, S>& b) {
+    // Natural tile order: workgroups go to the 8 XCDs round-robin, so with
+    // a multiple of 8 tiles per row the tiles above and below (which share
+    // halo rows) run on the same XCD and the whole chip sweeps one band of
+    // rows at a time.
     __shared__ Smem sm;
+    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
     const int tid = threadIdx.x;
     const int tx = tid % TX, ty = tid / TX;
-    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
-
     D psiC[N], psimu_d[N], dummy[N];
-    node1(sm, kd, b, x0, y0, tx + 2, ty + 2, psiC);
+    node1(sm, kd, b, kd, x0, y0, tx + 2, ty + 2, psiC);
     for (int r = tid; r < RING1; r += NT) {
       int lx, ly;
       ring1(r, lx, ly);
-      node1(sm, kd, b, x0, y0, lx, ly, dummy);
+      node1(sm, kd, b, kd, x0, y0, lx, ly, dummy);
     }
     __syncthreads();
-    node2(sm, kd, b, x0, y0, tx + 1, ty + 1, psimu_d);
+    node2(sm, kd, b, kd, x0, y0, tx + 1, ty + 1, psimu_d);
     for (int r = tid; r < RING2; r += NT) {
       int mx, my;
       ring2(r, mx, my);
-      node2(sm, kd, b, x0, y0, mx, my, dummy);
+      node2(sm, kd, b, kd, x0, y0, mx, my, dummy);
     }
     __syncthreads();
+    if (x0 + tx < k.nx && y0 + ty < k.ny)
+      node3(sm, kd, k, b, Grid{k.nx, k.ny, k.n, 0u}, x0, y0, tx, ty, psiC,
+            psimu_d);
+  }
+
+  // One TX x TY tile with its corner at (x0, y0) of box gd. Every thread of
+  // the workgroup passes both barriers; there is no early return, so a
+  // workgroup can process several tiles in a row.
+  __device__ static void tile(const Coef<D>& kd, const Coef<R>& k,
+                              const Bufs<Pop, S>& b, const Grid& gd, int x0,
+                              int y0) {
+    __shared__ Smem sm;
+    const int tid = threadIdx.x;
+    const int tx = tid % TX, ty = tid / TX;
+    D psiC[N], psimu_d[N], dummy[N];
+    node1(sm, kd, b, gd, x0, y0, tx + 2, ty + 2, psiC);
+    for (int r = tid; r < RING1; r += NT) {
+      int lx, ly;
+      ring1(r, lx, ly);
+      node1(sm, kd, b, gd, x0, y0, lx, ly, dummy);
+    }
+    __syncthreads();
+    node2(sm, kd, b, gd, x0, y0, tx + 1, ty + 1, psimu_d);
+    for (int r = tid; r < RING2; r += NT) {
+      int mx, my;
+      ring2(r, mx, my);
+      node2(sm, kd, b, gd, x0, y0, mx, my, dummy);
+    }
+    __syncthreads();
+    if (x0 + tx < gd.nx && y0 + ty < gd.ny)
+      node3(sm, kd, k, b, gd, x0, y0, tx, ty, psiC, psimu_d);
+  }
+
+  // Phase 3 for the own node (x0 + tx, y0 + ty) of the tile.
+  __device__ static inline void node3(const Smem& sm, const Coef<D>& kd,
+                                      const Coef<R>& k, const Bufs<Pop, S>& b,
+                                      const Grid& gd, int x0, int y0, int tx,
+                                      int ty, const D* psiC, const D* psimu_d) {
     R psimu[N];
 #pragma unroll
     for (int i = 0; i < N; ++i) psimu[i] = R(psimu_d[i]);
 
     const int gx = x0 + tx, gy = y0 + ty;
-    if (gx >= k.nx || gy >= k.ny) return;
-    const long long n = k.n;
-    const unsigned idx = unsigned(gy * k.nx + gx);
+    const long long n = gd.n;
+    const unsigned idx = gd.off + unsigned(gy * gd.nx + gx);
     const int lx = tx + 2, ly = ty + 2, mx = tx + 1, my = ty + 1;
 
     // ---- gradients from LDS -------------------------------------------
@@ -333,15 +390,15 @@ struct Step2D {
     R u[2], F[2] = {R(0), R(0)};
     R gp[Q];
     R sum_gm = R(0);
-    const Nbr nb = make_nbr(gx, gy, k.nx, k.ny);
+    const Nbr nb = make_nbr(gx, gy, gd.nx, gd.ny, gd.off);
     if constexpr (MODE == MODE_INIT) {
-      u[0] = b.inU ? R(b.inU[idx]) : R(0);
-      u[1] = b.inU ? R((b.inU + n)[idx]) : R(0);
+      u[0] = b.inU ? R(ldp(b.inU, idx)) : R(0);
+      u[1] = b.inU ? R(ldp(b.inU + n, idx)) : R(0);
     } else {
       R j[2] = {R(0), R(0)};
 #pragma unroll
       for (int p = 0; p < Q; ++p) {
-        gp[p] = ld<S, R>(&(b.gA + (long long)(p) * n)[nb.src(D2Q9::c[p].x, D2Q9::c[p].y)]);
+        gp[p] = R(ldp(b.gA + (long long)p * n, nb.src(D2Q9::c[p].x, D2Q9::c[p].y)));
         if (p > 0) sum_gm += gp[p];
         if (D2Q9::c[p].x) j[0] += R(D2Q9::c[p].x) * gp[p];
         if (D2Q9::c[p].y) j[1] += R(D2Q9::c[p].y) * gp[p];
@@ -349,7 +406,7 @@ struct Step2D {
       // force (eq. 3.13): -div T^{n-1} + sum_i phi mu_i grad C_i
       //                   + P^{n-1} grad psi + psi (rho a + G)
       const Patch<R> tp = patch(sm.T, mx, my);
-      const R Pprev = ld<S, R>(&(b.hist + (long long)((2 * N + 3)) * n)[idx]);
+      const R Pprev = R(ldp(b.hist + (long long)(2 * N + 3) * n, idx));
       R Fp[2];
       Fp[0] = grad_y(tp) + Pprev * gpsi[0] + psirho * k.accel[0] +
               psi * k.force[0];
@@ -378,7 +435,7 @@ struct Step2D {
     if constexpr (MODE != MODE_INIT) {
 #pragma unroll
       for (int q = 0; q < 3; ++q)
-        dtY[q] = Y[q] - ld<S, R>(&(b.hist + (long long)((2 * N + q)) * n)[idx]);
+        dtY[q] = Y[q] - R(ldp(b.hist + (long long)(2 * N + q) * n, idx));
     }
 
     // local flow rates from nu (eq. 16)
@@ -392,7 +449,7 @@ struct Step2D {
     const R A[3] = {psirho * u[0] * u[0] + Y[0], psirho * u[0] * u[1] + Y[1],
                     psirho * u[1] * u[1] + Y[2]};
     if constexpr (MODE == MODE_INIT) {
-      P = b.inP ? R(b.inP[idx]) : R(0);
+      P = b.inP ? R(ldp(b.inP, idx)) : R(0);
       psiP = psi * P;
     } else {
       // eq. (19)
@@ -406,10 +463,10 @@ struct Step2D {
 
     if constexpr (MODE == MODE_MOMENTS) {
 #pragma unroll
-      for (int i = 0; i < N; ++i) (b.outC + (long long)(i) * n)[idx] = double(C[i]);
-      b.outU[idx] = double(u[0]);
-      (b.outU + n)[idx] = double(u[1]);
-      b.outP[idx] = double(P);
+      for (int i = 0; i < N; ++i) stp(b.outC + (long long)(i) * n, idx, double(C[i]));
+      stp(b.outU, idx, double(u[0]));
+      stp(b.outU + n, idx, double(u[1]));
+      stp(b.outP, idx, double(P));
       return;
     }
 
@@ -426,7 +483,7 @@ struct Step2D {
         if (p == 0) geq -= psiP * k.inv_cs2;  // stored as g_0 - rho0
         // the buffers hold pre-streaming values: place g_p(x) where the
         // next pull reads it, at x - c_p
-        (b.gB + (long long)(p) * n)[nb.src(cx, cy)] = S(geq);
+        stp(b.gB + (long long)(p) * n, nb.src(cx, cy), Pop(geq));
       }
     } else {
       const R ub = u[0] * gprho[0] + u[1] * gprho[1];
@@ -440,7 +497,7 @@ struct Step2D {
       collide_flow<D2Q9>(gp, J, A, psiP, M, a0, F, s21, s22, k.sg, k.q4,
                          k.cs2, k.inv_cs2, del);
 #pragma unroll
-      for (int p = 0; p < Q; ++p) (b.gB + (long long)(p) * n)[idx] = S(gp[p] - del[p]);
+      for (int p = 0; p < Q; ++p) stp(b.gB + (long long)(p) * n, idx, Pop(gp[p] - del[p]));
     }
 
     // ---- phase sets: equilibrium (3.5), source (3.6, 3.7), collision ---
@@ -448,17 +505,20 @@ struct Step2D {
     for (int i = 0; i < N; ++i) {
       const R X[2] = {R(psiC[i]) * u[0], R(psiC[i]) * u[1]};
       const R em = k.eta[i] * psimu[i];
-      const S* fsrc = b.fA + (long long)i * Q * n;
-      S* fdst = b.fB + (long long)i * Q * n;
+      const Pop* fsrc = b.fA + (long long)i * Q * n;
+      Pop* fdst = b.fB + (long long)i * Q * n;
       if constexpr (MODE == MODE_INIT) {
-        // f^eq_0 = (w_0 - 1) eta phi mu + phi C (float64 rest plane)
-        (b.f0B + (long long)(i) * n)[idx] = (kd.wf[0] - D(1)) * kd.eta[i] * psimu_d[i] + psiC[i];
+        D comp = D(0);
 #pragma unroll
         for (int p = 1; p < Q; ++p) {
           const int cx = D2Q9::c[p].x, cy = D2Q9::c[p].y;
           const R feq = k.wf[p] * (em + (R(cx) * X[0] + R(cy) * X[1]) * k.inv_cs2);
-          (fdst + (long long)(p) * n)[nb.src(cx, cy)] = S(feq);
+          stp(fdst + (long long)(p) * n, nb.src(cx, cy), narrow<Pop>(feq, comp));
         }
+        // f^eq_0 = (w_0 - 1) eta phi mu + phi C (float64 rest plane), plus
+        // the storage rounding of the moving populations
+        stp(b.f0B + (long long)(i) * n, idx,
+            (kd.wf[0] - D(1)) * kd.eta[i] * psimu_d[i] + psiC[i] + comp);
       } else {
         // S_i = psi [(C_i sum_{j!=i} C_j - 1) grad mu_i
         //            - C_i sum_{j != i} C_j grad mu_j]     (eq. 3.7)
@@ -472,56 +532,65 @@ struct Step2D {
           }
         Sx *= psi;
         Sy *= psi;
-        const R dX0 = X[0] - ld<S, R>(&(b.hist + (long long)((2 * i)) * n)[idx]);
-        const R dX1 = X[1] - ld<S, R>(&(b.hist + (long long)((2 * i + 1)) * n)[idx]);
+        const R dX0 = X[0] - R(ldp(b.hist + (long long)(2 * i) * n, idx));
+        const R dX1 = X[1] - R(ldp(b.hist + (long long)(2 * i + 1) * n, idx));
         const R V[2] = {dX0 + k.cs2 * k.eta[i] * (mu[i] * gpsi[0] - Sx),
                         dX1 + k.cs2 * k.eta[i] * (mu[i] * gpsi[1] - Sy)};
         R fp[Q];
         fp[0] = R(0);
 #pragma unroll
         for (int p = 1; p < Q; ++p)
-          fp[p] = ld<S, R>(&(fsrc + (long long)(p) * n)[nb.src(D2Q9::c[p].x, D2Q9::c[p].y)]);
+          fp[p] = R(ldp(fsrc + (long long)(p) * n, nb.src(D2Q9::c[p].x, D2Q9::c[p].y)));
         R del[Q];
         collide_phase<D2Q9>(fp, em, X, V, k.sf, k.cs2, del);
-        (b.f0B + (long long)(i) * n)[idx] = (b.f0A + (long long)(i) * n)[idx] - D(del[0]);
+        D comp = D(0);
 #pragma unroll
-        for (int p = 1; p < Q; ++p) (fdst + (long long)(p) * n)[idx] = S(fp[p] - del[p]);
+        for (int p = 1; p < Q; ++p)
+          stp(fdst + (long long)(p) * n, idx, narrow<Pop>(fp[p] - del[p], comp));
+        stp(b.f0B + (long long)(i) * n, idx,
+            ldp(b.f0A + (long long)(i) * n, idx) - D(del[0]) + comp);
       }
-      (b.hist + (long long)((2 * i)) * n)[idx] = S(X[0]);
-      (b.hist + (long long)((2 * i + 1)) * n)[idx] = S(X[1]);
+      stp(b.hist + (long long)(2 * i) * n, idx, S(X[0]));
+      stp(b.hist + (long long)(2 * i + 1) * n, idx, S(X[1]));
     }
 #pragma unroll
-    for (int q = 0; q < 3; ++q) (b.hist + (long long)((2 * N + q)) * n)[idx] = S(Y[q]);
-    (b.hist + (long long)((2 * N + 3)) * n)[idx] = S(P);
-    b.TB[idx] = S(Tn);
+    for (int q = 0; q < 3; ++q) stp(b.hist + (long long)(2 * N + q) * n, idx, S(Y[q]));
+    stp(b.hist + (long long)(2 * N + 3) * n, idx, S(P));
+    stp(b.TB, idx, S(Tn));
   }
 };
 
-template <int N, class S, class R, int MODE, int TY>
+template <int N, class Pop, class S, class R, int MODE, int TY>
 __global__ __launch_bounds__(TX* TY) void k_step2d(Coef<double> kd, Coef<R> k,
-                                                    Bufs<S> b) {
-  Step2D<N, S, R, MODE, TY>::run(kd, k, b);
+                                                    Bufs<Pop, S> b) {
+  Step2D<N, Pop, S, R, MODE, TY>::run(kd, k, b);
 }
 
-template <int N, class S, class R, int MODE>
+template <int N, class Pop, class S, class R, int MODE>
 hipError_t launch_ty(const Coef<double>& kd, const Coef<R>& k,
-                     const Bufs<S>& b, int ty, hipStream_t st) {
+                     const Bufs<Pop, S>& b, int ty, hipStream_t st) {
   switch (ty) {
     case 4: {
       dim3 g((k.nx + TX - 1) / TX, (k.ny + 3) / 4);
-      hipLaunchKernelGGL((k_step2d<N, S, R, MODE, 4>), g, dim3(TX * 4), 0, st,
+      hipLaunchKernelGGL((k_step2d<N, Pop, S, R, MODE, 4>), g, dim3(TX * 4), 0, st,
+                         kd, k, b);
+      break;
+    }
+    case 16: {
+      dim3 g((k.nx + TX - 1) / TX, (k.ny + 15) / 16);
+      hipLaunchKernelGGL((k_step2d<N, Pop, S, R, MODE, 16>), g, dim3(TX * 16), 0, st,
                          kd, k, b);
       break;
     }
     case 2: {
       dim3 g((k.nx + TX - 1) / TX, (k.ny + 1) / 2);
-      hipLaunchKernelGGL((k_step2d<N, S, R, MODE, 2>), g, dim3(TX * 2), 0, st,
+      hipLaunchKernelGGL((k_step2d<N, Pop, S, R, MODE, 2>), g, dim3(TX * 2), 0, st,
                          kd, k, b);
       break;
     }
     default: {
       dim3 g((k.nx + TX - 1) / TX, (k.ny + 7) / 8);
-      hipLaunchKernelGGL((k_step2d<N, S, R, MODE, 8>), g, dim3(TX * 8), 0, st,
+      hipLaunchKernelGGL((k_step2d<N, Pop, S, R, MODE, 8>), g, dim3(TX * 8), 0, st,
                          kd, k, b);
       break;
     }
@@ -529,44 +598,157 @@ hipError_t launch_ty(const Coef<double>& kd, const Coef<R>& k,
   return hipGetLastError();
 }
 
-template <int N, class S, class R>
+template <int N, class Pop, class S, class R>
 hipError_t launch_mode(int mode, const Coef<double>& kd, const Coef<R>& k,
-                       const Bufs<S>& b, int ty, hipStream_t st) {
+                       const Bufs<Pop, S>& b, int ty, hipStream_t st) {
   switch (mode) {
     case MODE_STEP:
-      return launch_ty<N, S, R, MODE_STEP>(kd, k, b, ty, st);
+      return launch_ty<N, Pop, S, R, MODE_STEP>(kd, k, b, ty, st);
     case MODE_INIT:
-      return launch_ty<N, S, R, MODE_INIT>(kd, k, b, ty, st);
+      return launch_ty<N, Pop, S, R, MODE_INIT>(kd, k, b, ty, st);
     default:
-      return launch_ty<N, S, R, MODE_MOMENTS>(kd, k, b, ty, st);
+      return launch_ty<N, Pop, S, R, MODE_MOMENTS>(kd, k, b, ty, st);
   }
+}
+
+// ---- batches of independent boxes ----------------------------------------
+// Persistent step kernel over a work queue of (instance, tile) entries:
+// each workgroup takes the next tile index from *counter until the queue is
+// empty, then exits. Tiles of one step are independent, so no workgroup ever
+// waits for another; the counter must be zero at launch.
+template <int N, class Pop, class S, class R, int MODE, int TY>
+__global__ __launch_bounds__(TX* TY) void k_step2d_batch(
+    Coef<double> kd, Coef<R> k, Bufs<Pop, S> b, const BatchTile* tiles,
+    const BatchInst* insts, unsigned ntiles, unsigned* counter) {
+  __shared__ unsigned next;
+  for (;;) {
+    if (threadIdx.x == 0) next = atomicAdd(counter, 1u);
+    __syncthreads();
+    // the same value in every lane: make it a scalar so that the tile and
+    // instance descriptors are scalar loads
+    const unsigned t = __builtin_amdgcn_readfirstlane(next);
+    __syncthreads();
+    if (t >= ntiles) break;
+    const BatchTile tl = tiles[t];
+    const BatchInst in = insts[tl.inst];
+    Step2D<N, Pop, S, R, MODE, TY>::tile(
+        kd, k, b, Grid{in.nx, in.ny, k.n, unsigned(in.off)}, tl.x0, tl.y0);
+  }
+}
+
+template <int N, class Pop, class S, class R, int TY>
+hipError_t launch_batch_n(int mode, const Coef<double>& kd, const Coef<R>& k,
+                          const Bufs<Pop, S>& b, const BatchTile* tiles,
+                          const BatchInst* insts, unsigned ntiles,
+                          unsigned* counter, int nblocks, hipStream_t st) {
+  const dim3 g(nblocks), blk(TX * TY);
+  if (mode == MODE_INIT)
+    hipLaunchKernelGGL((k_step2d_batch<N, Pop, S, R, MODE_INIT, TY>), g, blk, 0,
+                       st, kd, k, b, tiles, insts, ntiles, counter);
+  else if (mode == MODE_MOMENTS)
+    hipLaunchKernelGGL((k_step2d_batch<N, Pop, S, R, MODE_MOMENTS, TY>), g, blk,
+                       0, st, kd, k, b, tiles, insts, ntiles, counter);
+  else
+    hipLaunchKernelGGL((k_step2d_batch<N, Pop, S, R, MODE_STEP, TY>), g, blk, 0,
+                       st, kd, k, b, tiles, insts, ntiles, counter);
+  return hipGetLastError();
+}
+
+template <int N, class Pop, class S, class R, int TY>
+int batch_blocks_n() {
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &per_cu, reinterpret_cast<const void*>(
+              &k_step2d_batch<N, Pop, S, R, MODE_STEP, TY>),
+          TX * TY, 0) != hipSuccess)
+    return 0;
+  return per_cu;
 }
 
 }  // namespace
 
-template <class S, class R>
+template <class Pop, class S, class R>
 hipError_t launch_2d(int nphase, int mode, const Coef<double>& kd,
-                     const Coef<R>& k, const Bufs<S>& b, int ty,
+                     const Coef<R>& k, const Bufs<Pop, S>& b, int ty,
                      hipStream_t st) {
   switch (nphase) {
     case 2:
-      return launch_mode<2, S, R>(mode, kd, k, b, ty, st);
+      return launch_mode<2, Pop, S, R>(mode, kd, k, b, ty, st);
     case 3:
-      return launch_mode<3, S, R>(mode, kd, k, b, ty, st);
+      return launch_mode<3, Pop, S, R>(mode, kd, k, b, ty, st);
     case 4:
-      return launch_mode<4, S, R>(mode, kd, k, b, ty, st);
+      return launch_mode<4, Pop, S, R>(mode, kd, k, b, ty, st);
     default:
       return hipErrorInvalidValue;
   }
 }
 
-template hipError_t launch_2d<double, double>(int, int, const Coef<double>&,
-                                              const Coef<double>&,
-                                              const Bufs<double>&, int,
-                                              hipStream_t);
-template hipError_t launch_2d<float, float>(int, int, const Coef<double>&,
-                                            const Coef<float>&,
-                                            const Bufs<float>&, int,
-                                            hipStream_t);
+template <class Pop, class S, class R>
+hipError_t launch_2d_batch(int nphase, int mode, const Coef<double>& kd,
+                           const Coef<R>& k,
+                           const Bufs<Pop, S>& b, const BatchTile* tiles,
+                           const BatchInst* insts, unsigned ntiles,
+                           unsigned* counter, int nblocks, int ty,
+                           hipStream_t st) {
+#define DDCC_BATCH_TY(NN)                                                      \
+  switch (ty) {                                                                \
+    case 4:                                                                    \
+      return launch_batch_n<NN, Pop, S, R, 4>(mode, kd, k, b, tiles, insts, ntiles,  \
+                                               counter, nblocks, st);          \
+    case 16:                                                                   \
+      return launch_batch_n<NN, Pop, S, R, 16>(mode, kd, k, b, tiles, insts, ntiles, \
+                                                counter, nblocks, st);         \
+    default:                                                                   \
+      return launch_batch_n<NN, Pop, S, R, 8>(mode, kd, k, b, tiles, insts, ntiles,  \
+                                               counter, nblocks, st);          \
+  }
+  switch (nphase) {
+    case 2:
+      DDCC_BATCH_TY(2)
+    case 3:
+      DDCC_BATCH_TY(3)
+    default:
+      return hipErrorInvalidValue;
+  }
+#undef DDCC_BATCH_TY
+}
+
+template <class Pop, class S, class R>
+int batch_blocks_per_cu(int nphase, int ty) {
+  if (nphase == 2)
+    return ty == 4 ? batch_blocks_n<2, Pop, S, R, 4>()
+                   : (ty == 16 ? batch_blocks_n<2, Pop, S, R, 16>()
+                               : batch_blocks_n<2, Pop, S, R, 8>());
+  if (nphase == 3)
+    return ty == 4 ? batch_blocks_n<3, Pop, S, R, 4>()
+                   : (ty == 16 ? batch_blocks_n<3, Pop, S, R, 16>()
+                               : batch_blocks_n<3, Pop, S, R, 8>());
+  return 0;
+}
+
+#define DDCC_BATCH_INST(P, S, R)                                              \
+  template hipError_t launch_2d_batch<P, S, R>(                               \
+      int, int, const Coef<double>&, const Coef<R>&, const Bufs<P, S>&,       \
+      const BatchTile*, const BatchInst*, unsigned, unsigned*, int, int,      \
+      hipStream_t);                                                           \
+  template int batch_blocks_per_cu<P, S, R>(int, int);
+DDCC_BATCH_INST(double, double, double)
+DDCC_BATCH_INST(float, float, float)
+DDCC_BATCH_INST(_Float16, float, float)
+DDCC_BATCH_INST(__bf16, float, float)
+#undef DDCC_BATCH_INST
+
+template hipError_t launch_2d<double, double, double>(
+    int, int, const Coef<double>&, const Coef<double>&,
+    const Bufs<double, double>&, int, hipStream_t);
+template hipError_t launch_2d<float, float, float>(
+    int, int, const Coef<double>&, const Coef<float>&,
+    const Bufs<float, float>&, int, hipStream_t);
+template hipError_t launch_2d<_Float16, float, float>(
+    int, int, const Coef<double>&, const Coef<float>&,
+    const Bufs<_Float16, float>&, int, hipStream_t);
+template hipError_t launch_2d<__bf16, float, float>(
+    int, int, const Coef<double>&, const Coef<float>&,
+    const Bufs<__bf16, float>&, int, hipStream_t);
 
 }  // namespace ddcc

@@ -18,6 +18,7 @@ template <class S>
 __global__ __launch_bounds__(kMassThreads) void k_mass(const double* f0,
                                                        const S* f, int N, int Q,
                                                        long long n,
+                                                       long long stride_n,
                                                        double* partial,
                                                        int* bad) {
   double acc[kMaxN] = {0.0, 0.0, 0.0, 0.0};
@@ -26,10 +27,10 @@ __global__ __launch_bounds__(kMassThreads) void k_mass(const double* f0,
   for (long long x = (long long)blockIdx.x * kMassThreads + threadIdx.x; x < n;
        x += stride) {
     for (int i = 0; i < N; ++i) {
-      const S* fi = f + (long long)i * Q * n + x;
-      double s = f0[(long long)i * n + x];
+      const S* fi = f + (long long)i * Q * stride_n + x;
+      double s = f0[(long long)i * stride_n + x];
       for (int p = 1; p < Q; ++p) {
-        const double v = double(fi[(long long)p * n]);
+        const double v = double(fi[(long long)p * stride_n]);
         s += v;
       }
       if (!isfinite(s)) nonfinite = 1;
@@ -67,14 +68,27 @@ __global__ void k_convert(const double* src, S* dst, long long count) {
     dst[i] = S(src[i]);
 }
 
+__global__ void k_fill_u32(unsigned* dst, unsigned v, long long count) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) dst[i] = v;
+}
+
 }  // namespace
+
+hipError_t launch_fill_u32(unsigned* dst, unsigned v, long long count,
+                           hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)((count + 255) / 256)),
+                     dim3(256), 0, st, dst, v, count);
+  return hipGetLastError();
+}
 
 template <class S>
 hipError_t launch_mass(const double* f0, const S* f, int nphase, int Q,
-                       long long n, double* partial, int* bad, int nblocks,
-                       hipStream_t st) {
+                       long long n, long long stride_n, double* partial,
+                       int* bad, int nblocks, hipStream_t st) {
   hipLaunchKernelGGL((k_mass<S>), dim3(nblocks), dim3(kMassThreads), 0, st, f0,
-                     f, nphase, Q, n, partial, bad);
+                     f, nphase, Q, n, stride_n, partial, bad);
   return hipGetLastError();
 }
 
@@ -89,12 +103,18 @@ hipError_t launch_convert(const double* src, S* dst, long long count,
   return hipGetLastError();
 }
 
-template hipError_t launch_mass<double>(const double*, const double*, int,
-                                        int, long long, double*, int*, int,
-                                        hipStream_t);
+template hipError_t launch_mass<double>(const double*, const double*, int, int,
+                                         long long, long long, double*,
+                                         int*, int, hipStream_t);
 template hipError_t launch_mass<float>(const double*, const float*, int, int,
-                                       long long, double*, int*, int,
-                                       hipStream_t);
+                                         long long, long long, double*,
+                                         int*, int, hipStream_t);
+template hipError_t launch_mass<_Float16>(const double*, const _Float16*, int, int,
+                                         long long, long long, double*,
+                                         int*, int, hipStream_t);
+template hipError_t launch_mass<__bf16>(const double*, const __bf16*, int, int,
+                                         long long, long long, double*,
+                                         int*, int, hipStream_t);
 template hipError_t launch_convert<double>(const double*, double*, long long,
                                            hipStream_t);
 template hipError_t launch_convert<float>(const double*, float*, long long,

@@ -25,7 +25,8 @@ DDCC_E_NONFINITE = 5
 DDCC_E_UNSUPPORTED = 6
 
 LATTICES = {"D2Q9": 0, "D3Q7": 1, "D3Q15": 2, "D3Q19": 3}
-FP64, FP32 = 0, 1
+FP64, FP32, FP16, BF16 = 0, 1, 2, 3
+PRECISIONS = {"fp64": FP64, "fp32": FP32, "fp16": FP16, "bf16": BF16}
 MAX_PHASES = 4
 RATE_SLOTS = ("0", "1", "21", "22", "3", "4")
 
@@ -84,6 +85,24 @@ def _load():
         "ddcc_last_error": (ctypes.c_char_p, [ctx]),
         "ddcc_destroy": (None, [ctx]),
         "ddcc_version": (ctypes.c_char_p, []),
+        "ddcc_batch_create": (ctypes.c_int, [P(ddcc_params), ctypes.c_int,
+                                             P(ctypes.c_int), P(ctypes.c_int),
+                                             vp, P(vp)]),
+        "ddcc_batch_init_geometry": (ctypes.c_int, [vp, ctypes.c_int, dp, dp]),
+        "ddcc_batch_init_fields": (ctypes.c_int, [vp, ctypes.c_int, dp, dp,
+                                                  dp]),
+        "ddcc_batch_step": (ctypes.c_int, [vp, ctypes.c_int64]),
+        "ddcc_batch_read_moments": (ctypes.c_int, [vp, ctypes.c_int, dp, dp,
+                                                   dp]),
+        "ddcc_batch_mass": (ctypes.c_int, [vp, ctypes.c_int, dp]),
+        "ddcc_batch_set_tile": (ctypes.c_int, [vp, ctypes.c_int]),
+        "ddcc_batch_autotune": (ctypes.c_int, [vp, ctypes.c_int,
+                                               P(ctypes.c_int)]),
+        "ddcc_batch_set_graph": (ctypes.c_int, [vp, ctypes.c_int]),
+        "ddcc_batch_sync": (ctypes.c_int, [vp]),
+        "ddcc_batch_time": (ctypes.c_int64, [vp]),
+        "ddcc_batch_last_error": (ctypes.c_char_p, [vp]),
+        "ddcc_batch_destroy": (None, [vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -113,6 +132,19 @@ ddcc_set_tile = LIB.ddcc_set_tile
 ddcc_last_error = LIB.ddcc_last_error
 ddcc_destroy = LIB.ddcc_destroy
 ddcc_version = LIB.ddcc_version
+ddcc_batch_create = LIB.ddcc_batch_create
+ddcc_batch_init_geometry = LIB.ddcc_batch_init_geometry
+ddcc_batch_init_fields = LIB.ddcc_batch_init_fields
+ddcc_batch_step = LIB.ddcc_batch_step
+ddcc_batch_read_moments = LIB.ddcc_batch_read_moments
+ddcc_batch_mass = LIB.ddcc_batch_mass
+ddcc_batch_set_tile = LIB.ddcc_batch_set_tile
+ddcc_batch_autotune = LIB.ddcc_batch_autotune
+ddcc_batch_set_graph = LIB.ddcc_batch_set_graph
+ddcc_batch_sync = LIB.ddcc_batch_sync
+ddcc_batch_time = LIB.ddcc_batch_time
+ddcc_batch_last_error = LIB.ddcc_batch_last_error
+ddcc_batch_destroy = LIB.ddcc_batch_destroy
 
 
 def make_params(dim, shape, nphase, lattice_f, lattice_g, precision="fp64",
@@ -133,7 +165,8 @@ def make_params(dim, shape, nphase, lattice_f, lattice_g, precision="fp64",
     p.nphase = nphase
     p.lattice_f = LATTICES[lattice_f]
     p.lattice_g = LATTICES[lattice_g]
-    p.precision = FP64 if precision in ("fp64", FP64) else FP32
+    p.precision = PRECISIONS[precision] if isinstance(precision, str) \
+        else int(precision)
     for key in ("d0", "eps", "m0", "rho0", "psi_min"):
         if key in prm:
             setattr(p, key, float(prm[key]))
@@ -283,6 +316,106 @@ class Sim:
             pass
 
 
+class Batch:
+    """A batch of independent 2D instances (ddcc_batch_*). Instance i has
+    the grid shapes[i] = (ny, nx); arrays are per instance, as for Sim."""
+
+    def __init__(self, params, shapes, stream=None):
+        self.params = params
+        self.nphase = params.nphase
+        self.shapes = [tuple(int(v) for v in sh) for sh in shapes]
+        ny = (ctypes.c_int * len(shapes))(*[sh[0] for sh in self.shapes])
+        nx = (ctypes.c_int * len(shapes))(*[sh[1] for sh in self.shapes])
+        h = ctypes.c_void_p()
+        st = ctypes.c_void_p(stream) if stream is not None else None
+        rc = LIB.ddcc_batch_create(ctypes.byref(params), len(shapes), nx, ny,
+                                   st, ctypes.byref(h))
+        if rc != DDCC_OK:
+            raise DDCCError(rc, "ddcc_batch_create failed")
+        self._h = h
+
+    @classmethod
+    def from_workloads(cls, wls, precision="fp32", stream=None):
+        """All workloads must share N and the method parameters."""
+        w0 = wls[0]
+        p = make_params(2, w0.shape, w0.nphase, "D2Q9", "D2Q9", precision,
+                        **w0.params)
+        b = cls(p, [w.shape for w in wls], stream)
+        for i, w in enumerate(wls):
+            b.init_geometry(i, w.psi, w.cos_theta_iN)
+            b.init_fields(i, w.C0, w.u0, w.P0)
+        return b
+
+    def _check(self, rc):
+        if rc != DDCC_OK:
+            raise DDCCError(rc, LIB.ddcc_batch_last_error(self._h).decode())
+
+    def init_geometry(self, i, psi, cos_theta=None):
+        psi = _c64(psi)
+        ct = None if cos_theta is None else _c64(cos_theta)
+        self._check(LIB.ddcc_batch_init_geometry(
+            self._h, int(i), _dptr(psi), None if ct is None else _dptr(ct)))
+
+    def init_fields(self, i, C, u=None, P=None):
+        C = _c64(C)
+        u = None if u is None else _c64(u)
+        P = None if P is None else _c64(P)
+        self._check(LIB.ddcc_batch_init_fields(
+            self._h, int(i), _dptr(C), None if u is None else _dptr(u),
+            None if P is None else _dptr(P)))
+
+    def step(self, n=1):
+        self._check(LIB.ddcc_batch_step(self._h, int(n)))
+
+    def read_moments(self, i):
+        sh = self.shapes[i]
+        C = np.empty((self.nphase,) + sh)
+        u = np.empty((2,) + sh)
+        P = np.empty(sh)
+        self._check(LIB.ddcc_batch_read_moments(self._h, int(i), _dptr(C),
+                                                _dptr(u), _dptr(P)))
+        return C, u, P
+
+    def mass(self, i):
+        m = np.empty(self.nphase)
+        self._check(LIB.ddcc_batch_mass(self._h, int(i), _dptr(m)))
+        return m
+
+    def set_tile(self, ty):
+        self._check(LIB.ddcc_batch_set_tile(self._h, int(ty)))
+
+    def autotune(self, steps=5):
+        ty = ctypes.c_int(0)
+        self._check(LIB.ddcc_batch_autotune(self._h, int(steps),
+                                            ctypes.byref(ty)))
+        return ty.value
+
+    def set_graph(self, steps_per_graph):
+        self._check(LIB.ddcc_batch_set_graph(self._h, int(steps_per_graph)))
+
+    def sync(self):
+        self._check(LIB.ddcc_batch_sync(self._h))
+
+    @property
+    def time(self):
+        return int(LIB.ddcc_batch_time(self._h))
+
+    @property
+    def nodes(self):
+        return int(sum(a * b for a, b in self.shapes))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            LIB.ddcc_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def unpack_state(sim, buf):
     """Split a ddcc_save checkpoint into arrays (host side, for tests):
     f (N, Qf, *shape), g (Qg, *shape) with g_0 stored as g_0 - rho0,
@@ -295,23 +428,31 @@ def unpack_state(sim, buf):
     Qf, Qg = qs[lf], qs[lg]
     shape = (ny, nx) if dim == 2 else (nz, ny, nx)
     n = nx * ny * nz
-    dt = np.float64 if prec == FP64 else np.float32
     nhist = N * dim + dim * (dim + 1) // 2 + 1
     nT = dim * (dim - 1) // 2
-    esz = 8 if prec == FP64 else 4
+    fdt = np.float64 if prec == FP64 else np.float32      # fields
+    pdt = {FP64: np.float64, FP32: np.float32, FP16: np.float16,
+           BF16: np.uint16}[prec]                         # populations
+    psz = np.dtype(pdt).itemsize
     raw = bytes(buf[56:])
-    f = np.frombuffer(raw[:N * Qf * n * esz], dtype=dt).reshape(
-        (N, Qf) + shape).astype(np.float64)
-    f0 = np.frombuffer(raw[N * Qf * n * esz:N * Qf * n * esz + N * n * 8],
-                       dtype=np.float64).reshape((N,) + shape)
-    f[:, 0] = f0            # the rest populations live in a float64 plane
-    data = np.frombuffer(raw[N * Qf * n * esz + N * n * 8:], dtype=dt)
-    o = 0
-    g = data[o:o + Qg * n].reshape((Qg,) + shape)
-    o += Qg * n
-    hist = data[o:o + nhist * n].reshape((nhist,) + shape)
-    o += nhist * n
-    T = data[o:o + nT * n].reshape((nT,) + shape)
+
+    def pops(offset, count):
+        a = np.frombuffer(raw[offset:offset + count * psz], pdt)
+        if prec == BF16:      # bfloat16 is the high half of a float32
+            a = (a.astype(np.uint32) << 16).view(np.float32)
+        return a.astype(np.float64)
+
+    npop = N * Qf * n
+    f = pops(0, npop).reshape((N, Qf) + shape)
+    o = npop * psz
+    f[:, 0] = np.frombuffer(raw[o:o + N * n * 8], np.float64).reshape(
+        (N,) + shape)       # the rest populations live in a float64 plane
+    o += N * n * 8
+    g = pops(o, Qg * n).reshape((Qg,) + shape)
+    o += Qg * n * psz
+    data = np.frombuffer(raw[o:], dtype=fdt)
+    hist = data[:nhist * n].reshape((nhist,) + shape)
+    T = data[nhist * n:(nhist + nT) * n].reshape((nT,) + shape)
     return dict(f=f, g=g, hist=hist, T=T, t=t, dim=dim, N=N, lf=lf, lg=lg)
 
 

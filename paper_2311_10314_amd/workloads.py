@@ -34,6 +34,7 @@ class Workload:
         self.u0 = u0
         self.P0 = P0
         self.steps = steps
+        self.walls = None    # several walls: [(psi_k, cos theta^k_iN)]
 
     @property
     def nphase(self):
@@ -209,6 +210,100 @@ def droplet_impact_sphere_3d(n=256, steps=5000):
     prm = default_params(3, 2, rho=[10.0, 1.0])
     return Workload("droplet_sphere_3d", 3, shape, "D3Q15", "D3Q19", prm,
                     psi, ct, C0, u0, np.zeros(shape), steps)
+
+
+def wavy_channel_2d(n=256, theta_bottom=(120.0, 60.0), theta_top=(120.0, 60.0),
+                    amplitude=None, steps=2000):
+    """2D, N = 3, two walls with their own wetting angles (Section 4.5): the
+    bottom wall y = n/4 + B(x) and the top wall y = 3n/4 - B(x) of a
+    periodic wavy channel, B(x) = 0.05 n sin(4 pi x / n) (the paper's
+    sqrt-modulated profile is not periodic), each wall its own smooth
+    characteristic function psi_k and angles (theta^k_13, theta^k_23); a
+    compound droplet (inner phase 1 of radius n/10, outer phase 2 of radius
+    n/6, phase 3 around) at the channel centre, pushed along x by a body
+    force density. Returns the walls in `walls` (psi_k, cos theta^k_iN)."""
+    shape = (n, n)
+    x, y = _grid(shape)
+    A = 0.05 * n if amplitude is None else amplitude
+    B = A * np.sin(4.0 * math.pi * x / n)
+    psi1 = psi_from_distance(y - (n / 4.0 + B))
+    psi2 = psi_from_distance((3.0 * n / 4.0 - B) - y)
+    walls = []
+    for psi_k, th in ((psi1, theta_bottom), (psi2, theta_top)):
+        ct = np.stack([np.full(shape, math.cos(math.radians(t))) for t in th])
+        walls.append((psi_k, ct))
+    r = periodic_distance((x, y), (n / 2.0, n / 2.0), shape)
+    eps = 5.0
+    inner = droplet(r, n / 10.0, eps)
+    outer = droplet(r, n / 6.0, eps)
+    C1 = inner
+    C2 = np.clip(outer - inner, 0.0, 1.0)
+    C3 = 1.0 - C1 - C2
+    prm = default_params(2, 3, rho=[1.0, 1.0, 0.1], force=[1e-6, 0.0])
+    wl = Workload("wavy_channel_2d", 2, shape, "D2Q9", "D2Q9", prm,
+                  psi1 * psi2, walls[0][1], np.stack([C1, C2, C3]),
+                  np.zeros((2,) + shape), np.zeros(shape), steps)
+    wl.walls = walls
+    return wl
+
+
+BATCH_SIDES = (64, 96, 128, 192, 256)
+
+
+def batched_instance(k, seed=2313, steps=2000):
+    """Instance k of the batched workload: 2D, N = 2, grid sides drawn
+    independently from BATCH_SIDES, 1-8 non-overlapping solid disks with
+    radii U[0.05, 0.12] min(nx, ny), one droplet of radius U[8, 24] clear of
+    the disks, wetting angle U[30, 150] deg, interface width eps = 4. Seeded
+    by (seed, k), so any subset of the batch can be rebuilt alone."""
+    rng = np.random.default_rng([seed, k])
+    nx = int(rng.choice(BATCH_SIDES))
+    ny = int(rng.choice(BATCH_SIDES))
+    shape = (ny, nx)
+    x, y = _grid(shape)
+    m = min(nx, ny)
+    eps0 = 2.0 * math.sqrt(2.0) * PSI_WIDTH
+    n_disks = int(rng.integers(1, 9))
+    centres, radii = [], []
+    tries = 0
+    while len(centres) < n_disks and tries < 20000:
+        tries += 1
+        c = (rng.uniform(0, nx), rng.uniform(0, ny))
+        r = rng.uniform(0.05, 0.12) * m
+        if all(math.hypot(_periodic_delta(c[0], c2[0], nx),
+                          _periodic_delta(c[1], c2[1], ny)) >= r + r2 + 2 * eps0
+               for c2, r2 in zip(centres, radii)):
+            centres.append(c)
+            radii.append(r)
+    psi = np.ones(shape)
+    for c, r in zip(centres, radii):
+        psi = psi * psi_from_distance(periodic_distance((x, y), c, shape) - r)
+    eps = 4.0
+    R = rng.uniform(8.0, 24.0)
+    R = min(R, 0.3 * m)
+    best, best_c = -np.inf, (nx / 2.0, ny / 2.0)
+    for _ in range(200):          # the candidate centre farthest from walls
+        c = (rng.uniform(0, nx), rng.uniform(0, ny))
+        gap = min([math.hypot(_periodic_delta(c[0], c2[0], nx),
+                              _periodic_delta(c[1], c2[1], ny)) - r2 - R
+                   for c2, r2 in zip(centres, radii)] + [np.inf])
+        if gap > best:
+            best, best_c = gap, c
+        if gap > eps0 + eps:
+            break
+    C1 = droplet(periodic_distance((x, y), best_c, shape), R, eps)
+    theta = rng.uniform(30.0, 150.0)
+    ct = np.full((1,) + shape, math.cos(math.radians(theta)))
+    prm = default_params(2, 2, eps=eps)
+    return Workload("batch_%d" % k, 2, shape, "D2Q9", "D2Q9", prm, psi, ct,
+                    np.stack([C1, 1.0 - C1]), np.zeros((2,) + shape),
+                    np.zeros(shape), steps)
+
+
+def batched_instances(count=256, seed=2313, steps=2000):
+    """The batched workload: `count` independent instances (see
+    batched_instance) that share N and the method parameters."""
+    return [batched_instance(k, seed, steps) for k in range(count)]
 
 
 def random_small(dim, N, shape, seed, lattice_f=None, lattice_g=None,

@@ -104,3 +104,29 @@ def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
     mod = importlib.util.module_from_spec(spec)
     with pytest.raises(ImportError):
         spec.loader.exec_module(mod)
+
+
+def test_batch_create_rejects_bad_arguments():
+    """Rejected before any device call: no instances, an empty grid, 3D
+    parameters, invalid method parameters, NULL handles."""
+    from paper_2311_10314_amd import ddcc
+    h = ctypes.c_void_p()
+    nx = (ctypes.c_int * 2)(64, 96)
+    ny = (ctypes.c_int * 2)(64, 0)
+    p = _params()
+    assert ddcc.ddcc_batch_create(ctypes.byref(p), 0, nx, nx, None,
+                                  ctypes.byref(h)) == ddcc.DDCC_E_INVAL
+    assert ddcc.ddcc_batch_create(ctypes.byref(p), 2, nx, ny, None,
+                                  ctypes.byref(h)) == ddcc.DDCC_E_INVAL
+    p3 = _params(dim=3, nz=8, lattice_f=2, lattice_g=3)
+    assert ddcc.ddcc_batch_create(ctypes.byref(p3), 2, nx, nx, None,
+                                  ctypes.byref(h)) == ddcc.DDCC_E_UNSUPPORTED
+    pb = _params(d0=1.5)
+    assert ddcc.ddcc_batch_create(ctypes.byref(pb), 2, nx, nx, None,
+                                  ctypes.byref(h)) == ddcc.DDCC_E_INVAL
+    assert h.value is None
+    assert ddcc.ddcc_batch_step(None, 1) == ddcc.DDCC_E_INVAL
+    assert ddcc.ddcc_batch_set_graph(None, 2) == ddcc.DDCC_E_INVAL
+    assert ddcc.ddcc_batch_time(None) == -1
+    assert ddcc.ddcc_batch_last_error(None) == b"NULL batch"
+    ddcc.ddcc_batch_destroy(None)

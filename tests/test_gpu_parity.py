@@ -74,7 +74,7 @@ def test_short_run_fp64(k):
     assert drift.max() < 1e-12
 
 
-@pytest.mark.parametrize("tile", [2, 4, 8])
+@pytest.mark.parametrize("tile", [2, 4, 8, 16])
 def test_tile_shape_invariance_fp64(tile):
     """Different tile heights give identical results (LDS halos consistent)."""
     wl = small_cases()[1]
@@ -90,13 +90,13 @@ def test_disk_droplet_1000_steps_fp64():
     o = oracle_run(wl, 1000)
     g = gpu_run(wl, 1000)
     e = _report("disk 1000", g, o)
-    # P = phi P / phi: deep inside the solid (phi down to 1e-13) it is
-    # round-off divided by phi, so P is compared where phi >= 1e-3 and
-    # phi P everywhere.
-    fl = wl.psi >= 1e-3
+    # P = phi P / phi: its error is that of phi P divided by phi, so deep in
+    # the solid (phi down to 1e-13) it is round-off over phi. phi P is
+    # compared everywhere and P where phi >= 1e-2 (amplification <= 100).
+    fl = wl.psi >= 1e-2
     eP = rel_linf(g["P"][fl], o["P"][fl])
     epP = rel_linf(wl.psi * g["P"], wl.psi * o["P"])
-    print("P(psi>=1e-3) %.2e  psi*P %.2e" % (eP, epP), flush=True)
+    print("P(psi>=1e-2) %.2e  psi*P %.2e" % (eP, epP), flush=True)
     assert e["C"] < 1e-10 and e["u"] < 1e-10 and eP < 1e-10 and epP < 1e-10
     drift = np.abs(g["mass"] - g["mass0"]) / np.abs(g["mass0"])
     assert drift.max() < 1e-12

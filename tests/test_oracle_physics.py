@@ -283,3 +283,73 @@ def test_contact_angle_flat_wall():
     assert abs(_cap_angle(60, 60) - 60) < 2.0
     assert _cap_angle(90, 60) < 90 - 1.5
     assert _cap_angle(90, 120) > 90 + 1.5
+
+
+# ---------------------------------------------------------------------------
+# Several walls (Section 4.5): psi = prod_k psi_k, wetting per wall
+# ---------------------------------------------------------------------------
+def _band_walls(ny, nx, y_bottom, y_top, thick=16.0):
+    """Two solid bands 'thick' cells thick: band 1 ends at y_bottom (its top
+    face is the channel's bottom wall), band 2 starts at y_top. Each band's
+    psi_k is smooth and periodic on its own (fluid on both sides of both
+    bands), as a wall's characteristic function must be."""
+    x, y = W._grid((ny, nx))
+    shape = (ny, nx)
+    c1 = (0.0, y_bottom - thick / 2)
+    c2 = (0.0, y_top + thick / 2)
+    d1 = np.abs(W._periodic_delta(y, c1[1], ny)) - thick / 2
+    d2 = np.abs(W._periodic_delta(y, c2[1], ny)) - thick / 2
+    return x, y, W.psi_from_distance(d1), W.psi_from_distance(d2)
+
+
+def test_two_separated_walls_with_one_angle_match_one_wall():
+    """Two solid bands 16 cells thick, 36 and 28 cells apart, with the same
+    angle: the per-wall sum cos theta |grad psi_1| + cos theta |grad psi_2|
+    equals cos theta |grad(psi_1 psi_2)| wherever the walls' tails do not
+    overlap, so the two descriptions evolve alike (to the exp(-24)-small
+    overlap); the droplet stays within one band and the channel."""
+    ny, nx, yw = 96, 48, 26.0
+    x, y, pb, pt = _band_walls(ny, nx, yw, 62.0)
+    prm = params_2d()
+    ct = np.full((1, ny, nx), math.cos(math.radians(60.0)))
+    C1 = W.droplet(np.sqrt((x - nx / 2) ** 2 + (y - yw) ** 2), 12.0, prm.eps)
+    C0 = np.array([C1, 1 - C1])
+    g1 = O.Geometry(prm, pb * pt, ct)
+    g2 = O.Geometry(prm, None, None, walls=[(pb, ct), (pt, ct)])
+    assert np.array_equal(g1.psi, g2.psi)
+    s1 = O.run(prm, g1, O.init_state(prm, g1, C0), 100)
+    s2 = O.run(prm, g2, O.init_state(prm, g2, C0), 100)
+    Ca, ua, _ = O.moments(prm, g1, s1)
+    Cb, ub, _ = O.moments(prm, g2, s2)
+    assert np.abs(Ca - Cb).max() < 1e-9
+    # the walls' tails meet in the 28-cell channel across the periodic
+    # boundary (weights differ by ~4e-6 there), which shows up in u at the
+    # 1e-8 level
+    assert np.abs(ua - ub).max() < 1e-7 * np.abs(ua).max()
+
+
+def test_each_wall_wets_with_its_own_angle():
+    """A 90-deg cap on the bottom wall of a channel whose bottom wall has
+    60 deg and top wall 120 deg spreads (its angle falls); with the two
+    walls' angles swapped it contracts. Taking the other wall's angle, or
+    one angle for both, breaks one of the two."""
+    ny, nx, yw, R = 80, 64, 22.0, 12.0
+    x, y, pb, pt = _band_walls(ny, nx, yw, 52.0)
+    prm = params_2d()
+    C1 = W.droplet(np.sqrt((x - nx / 2) ** 2 + (y - yw) ** 2), R, prm.eps)
+    C0 = np.array([C1, 1 - C1])
+    angles = []
+    for th_b, th_t in ((60.0, 120.0), (120.0, 60.0)):
+        cb = np.full((1, ny, nx), math.cos(math.radians(th_b)))
+        ctp = np.full((1, ny, nx), math.cos(math.radians(th_t)))
+        geo = O.Geometry(prm, None, None, walls=[(pb, cb), (pt, ctp)])
+        st = O.run(prm, geo, O.init_state(prm, geo, C0), 1000)
+        C = O.moments(prm, geo, st)[0][0]
+        p = _contour(C, yw + 3)
+        A = np.c_[2 * p[:, 0], 2 * p[:, 1], np.ones(len(p))]
+        (xc, ycf, c), *_ = np.linalg.lstsq(A, (p ** 2).sum(axis=1),
+                                           rcond=None)
+        Rf = math.sqrt(c + xc * xc + ycf * ycf)
+        angles.append(math.degrees(math.acos(max(-1.0, min(1.0,
+                                                           (yw - ycf) / Rf)))))
+    assert angles[0] < 90 - 1.5 and angles[1] > 90 + 1.5, angles
