@@ -68,6 +68,7 @@ extern "C" {
                         DDCC_FP16                                        */
 
 #define DDCC_MAX_PHASES 4
+#define DDCC_MAX_WALLS 8
 
 /* Rate slots of s_f[] and s_g[]: the diagonal of S (Section 3 lattice
  * tables): s0, s1, s21, s22, s3, s4. For the flow set s_g[2] and s_g[3] are
@@ -83,7 +84,8 @@ typedef struct ddcc_params {
   int dim;          /* 2 or 3                                               */
   int nx, ny, nz;   /* grid size; nz = 1 when dim = 2; all >= 1             */
   int nphase;       /* N, 2 <= N <= DDCC_MAX_PHASES                          */
-  int lattice_f;    /* velocity set of the phase sets (DDCC_D2Q9 / D3Q15)    */
+  int lattice_f;    /* velocity set of the phase sets: DDCC_D2Q9 in 2D,
+                       DDCC_D3Q15 or DDCC_D3Q7 (needs d0 < 1/3) in 3D     */
   int lattice_g;    /* velocity set of the flow set   (DDCC_D2Q9 / D3Q19)    */
   int precision;    /* DDCC_FP64, DDCC_FP32, DDCC_FP16 or DDCC_BF16          */
   double d0;        /* c_s^2 / c^2, inside the lattices' positive-weight range */
@@ -125,6 +127,17 @@ int ddcc_create(const ddcc_params* p, void* stream, ddcc_ctx** out);
  * [-1, 1]; NULL means 90 degrees everywhere. Must precede ddcc_init_fields. */
 int ddcc_init_geometry(ddcc_ctx* ctx, const double* psi,
                        const double* cos_theta);
+
+/* Static geometry of several walls (Section 4.5): psi [nwalls][nz][ny][nx],
+ * the smooth characteristic function psi_k of each wall, and cos_theta
+ * [nwalls][N-1][nz][ny][nx], each wall's own contact angles theta^k_iN (NULL:
+ * 90 degrees). The box's characteristic function is psi = prod_k psi_k and
+ * the wetting term of eq. (2.14) sums cos theta^k_jq |grad psi_k| over the
+ * walls; each psi_k must be smooth on the periodic box by itself (fluid on
+ * both sides of a band). ddcc_init_geometry is the case nwalls = 1.
+ * 1 <= nwalls <= DDCC_MAX_WALLS. Synchronises. */
+int ddcc_init_geometry_walls(ddcc_ctx* ctx, int nwalls, const double* psi,
+                             const double* cos_theta);
 int ddcc_init_geometry_dev(ddcc_ctx* ctx, const double* psi_dev,
                            const double* cos_theta_dev);
 

@@ -30,7 +30,7 @@ struct ddcc_ctx {
   void* T[2] = {nullptr, nullptr};
   void* hist = nullptr;
   void* psi = nullptr;
-  void* ct = nullptr;
+  void* wet = nullptr;         // wetting weights [N-1][n]
   double* work = nullptr;     // 3D: C_i and mu_i fields, 2 N n float64
   double* staging = nullptr;  // (N + dim + 1) * n float64, lazily
   double* partial = nullptr;
@@ -331,7 +331,7 @@ Bufs<Pop, S> bufs(ddcc_ctx* c, int mode) {
   }
   b.hist = static_cast<S*>(c->hist);
   b.psi = static_cast<const S*>(c->psi);
-  b.ct = static_cast<const S*>(c->ct);
+  b.wet = static_cast<const S*>(c->wet);
   if (c->work) {
     b.fC = c->work;
     b.fmu = c->work + (size_t)c->p.nphase * c->n;
@@ -353,8 +353,8 @@ hipError_t launch_as(ddcc_ctx* c, const Coef<R>& k, int mode,
   if (c->p.dim == 2)
     return launch_2d<Pop, S, R>(c->p.nphase, mode, c->kd, k, b, c->tile_y,
                                 c->stream);
-  return launch_3d<Pop, S, R>(c->p.nphase, mode, c->kd, k, b, c->tile_x,
-                              c->tile_y, c->stream);
+  return launch_3d<Pop, S, R>(c->p.nphase, c->p.lattice_f, mode, c->kd, k, b,
+                              c->tile_x, c->tile_y, c->stream);
 }
 
 hipError_t launch(ddcc_ctx* c, int mode, const double* inC, const double* inU,
@@ -407,7 +407,7 @@ int upload(ddcc_ctx* c, const double* src, void* dst, size_t count) {
 void release(ddcc_ctx* c) {
   void* ptrs[] = {c->f[0],  c->f[1],   c->f0[0],    c->f0[1], c->g[0],
                   c->g[1],  c->T[0],   c->T[1],     c->hist,  c->psi,
-                  c->ct,    c->staging, c->partial, c->bad,  c->work};
+                  c->wet,   c->staging, c->partial, c->bad,  c->work};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
@@ -512,7 +512,7 @@ int ddcc_create(const ddcc_params* p, void* stream, ddcc_ctx** out) {
   if (e == hipSuccess) e = hipMalloc(&c->hist, (size_t)c->nhist * n * c->esz);
   if (e == hipSuccess) e = hipMalloc(&c->psi, n * c->esz);
   if (e == hipSuccess)
-    e = hipMalloc(&c->ct, (size_t)(p->nphase - 1) * n * c->esz);
+    e = hipMalloc(&c->wet, (size_t)(p->nphase - 1) * n * c->esz);
   if (e == hipSuccess && p->dim == 3)
     e = hipMalloc(&c->work, (size_t)2 * p->nphase * n * sizeof(double));
   long long mb = (c->n + 255) / 256;
@@ -529,7 +529,8 @@ int ddcc_create(const ddcc_params* p, void* stream, ddcc_ctx** out) {
   if (p->dim == 3) {
     // The 3D kernels are built per (phase, flow) lattice pair; the host
     // checks the pair here so that create fails early when it is absent.
-    if (!(p->lattice_f == DDCC_D3Q15 && p->lattice_g == DDCC_D3Q19) ||
+    if (!((p->lattice_f == DDCC_D3Q15 || p->lattice_f == DDCC_D3Q7) &&
+          p->lattice_g == DDCC_D3Q19) ||
         p->nphase > 3 || !have_3d()) {
       release(c);
       delete c;
@@ -540,61 +541,79 @@ int ddcc_create(const ddcc_params* p, void* stream, ddcc_ctx** out) {
   return DDCC_OK;
 }
 
-int ddcc_init_geometry(ddcc_ctx* c, const double* psi, const double* ct) {
-  if (!c) return DDCC_E_INVAL;
-  if (!psi) return fail(c, DDCC_E_INVAL, "psi is NULL");
-  const size_t n = (size_t)c->n;
-  for (size_t i = 0; i < n; ++i)
-    if (!(psi[i] >= 0.0 && psi[i] <= 1.0))
-      return fail(c, DDCC_E_INVAL, "psi must be finite and in [0, 1]");
-  const size_t nct = (size_t)(c->p.nphase - 1) * n;
-  std::vector<double> zeros;
-  if (ct) {
-    for (size_t i = 0; i < nct; ++i)
-      if (!(ct[i] >= -1.0 && ct[i] <= 1.0))
-        return fail(c, DDCC_E_INVAL, "cos_theta must be finite and in [-1, 1]");
-  } else {
-    zeros.assign(nct, 0.0);
-    ct = zeros.data();
-  }
-  int rc = upload(c, psi, c->psi, n);
-  if (rc) return rc;
-  rc = upload(c, ct, c->ct, nct);
-  if (rc) return rc;
+// Geometry of K walls from float64 device arrays psik [K][n] and ctk
+// [K][N-1][n] (NULL: 90 degrees): psi and the wetting weights in the
+// context's field precision.
+static int geometry_from_device(ddcc_ctx* c, int K, const double* psik,
+                                const double* ctk) {
+  const int nm1 = c->p.nphase - 1;
+  hipError_t e =
+      c->p.precision == DDCC_FP64
+          ? launch_wet_field<double>(psik, ctk, K, nm1, c->p.nx, c->p.ny,
+                                     c->p.nz, static_cast<double*>(c->psi),
+                                     static_cast<double*>(c->wet), c->n, 0,
+                                     c->stream)
+          : launch_wet_field<float>(psik, ctk, K, nm1, c->p.nx, c->p.ny,
+                                    c->p.nz, static_cast<float*>(c->psi),
+                                    static_cast<float*>(c->wet), c->n, 0,
+                                    c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "geometry kernel");
   c->geom_ok = true;
   c->fields_ok = false;
   return DDCC_OK;
 }
 
+// Checks K walls on the host (psi_k in [0, 1], cosines in [-1, 1]).
+static int check_walls(ddcc_ctx* c, int K, const double* psik,
+                       const double* ctk) {
+  if (K < 1 || K > DDCC_MAX_WALLS)
+    return fail(c, DDCC_E_INVAL, "number of walls must be in [1, 8]");
+  if (!psik) return fail(c, DDCC_E_INVAL, "psi is NULL");
+  const size_t n = (size_t)c->n;
+  for (size_t i = 0; i < (size_t)K * n; ++i)
+    if (!(psik[i] >= 0.0 && psik[i] <= 1.0))
+      return fail(c, DDCC_E_INVAL, "psi must be finite and in [0, 1]");
+  if (ctk)
+    for (size_t i = 0; i < (size_t)K * (c->p.nphase - 1) * n; ++i)
+      if (!(ctk[i] >= -1.0 && ctk[i] <= 1.0))
+        return fail(c, DDCC_E_INVAL, "cos_theta must be finite and in [-1, 1]");
+  return DDCC_OK;
+}
+
+int ddcc_init_geometry_walls(ddcc_ctx* c, int nwalls, const double* psi,
+                             const double* cos_theta) {
+  if (!c) return DDCC_E_INVAL;
+  int rc = check_walls(c, nwalls, psi, cos_theta);
+  if (rc) return rc;
+  const size_t n = (size_t)c->n, np = (size_t)nwalls * n;
+  const size_t nc = cos_theta ? np * (c->p.nphase - 1) : 0;
+  double* d = nullptr;
+  HIPCHK(c, hipMalloc(&d, (np + nc) * sizeof(double)), "hipMalloc geometry");
+  hipError_t e = hipMemcpyAsync(d, psi, np * sizeof(double),
+                                hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess && nc)
+    e = hipMemcpyAsync(d + np, cos_theta, nc * sizeof(double),
+                       hipMemcpyHostToDevice, c->stream);
+  if (e != hipSuccess) {
+    (void)hipFree(d);
+    return hip_fail(c, e, "copy geometry");
+  }
+  rc = geometry_from_device(c, nwalls, d, nc ? d + np : nullptr);
+  e = hipStreamSynchronize(c->stream);
+  (void)hipFree(d);
+  if (rc) return rc;
+  if (e != hipSuccess) return hip_fail(c, e, "sync");
+  return DDCC_OK;
+}
+
+int ddcc_init_geometry(ddcc_ctx* c, const double* psi, const double* ct) {
+  return ddcc_init_geometry_walls(c, 1, psi, ct);
+}
+
 int ddcc_init_geometry_dev(ddcc_ctx* c, const double* psi, const double* ct) {
   if (!c) return DDCC_E_INVAL;
   if (!psi) return fail(c, DDCC_E_INVAL, "psi is NULL");
-  const long long n = c->n;
-  const long long nct = (long long)(c->p.nphase - 1) * n;
-  hipError_t e;
-  if (c->p.precision == DDCC_FP64) {
-    e = launch_convert<double>(psi, static_cast<double*>(c->psi), n, c->stream);
-    if (e == hipSuccess) {
-      if (ct)
-        e = launch_convert<double>(ct, static_cast<double*>(c->ct), nct,
-                                   c->stream);
-      else
-        e = hipMemsetAsync(c->ct, 0, nct * sizeof(double), c->stream);
-    }
-  } else {
-    e = launch_convert<float>(psi, static_cast<float*>(c->psi), n, c->stream);
-    if (e == hipSuccess) {
-      if (ct)
-        e = launch_convert<float>(ct, static_cast<float*>(c->ct), nct,
-                                  c->stream);
-      else
-        e = hipMemsetAsync(c->ct, 0, nct * sizeof(float), c->stream);
-    }
-  }
-  if (e != hipSuccess) return hip_fail(c, e, "init_geometry_dev");
-  c->geom_ok = true;
-  c->fields_ok = false;
-  return DDCC_OK;
+  return geometry_from_device(c, 1, psi, ct);
 }
 
 static int init_fields_common(ddcc_ctx* c, const double* C, const double* u,
@@ -899,7 +918,7 @@ struct ddcc_batch {
   void* T[2] = {nullptr, nullptr};
   void* hist = nullptr;
   void* psi = nullptr;
-  void* ct = nullptr;
+  void* wet = nullptr;        // wetting weights [N-1][ntot]
   double* staging = nullptr;  // (N + 3) planes of ntot float64
   double* partial = nullptr;
   int* bad = nullptr;
@@ -957,7 +976,7 @@ void batch_release(ddcc_batch* b) {
   drop_graphs(b);
   void* ptrs[] = {b->f[0],   b->f[1], b->f0[0],    b->f0[1],    b->g[0],
                   b->g[1],   b->T[0], b->T[1],     b->hist,     b->psi,
-                  b->ct,     b->staging, b->partial, b->bad, b->tiles,
+                  b->wet,    b->staging, b->partial, b->bad, b->tiles,
                   b->insts,  b->counters};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
@@ -1019,7 +1038,7 @@ Bufs<Pop, S> batch_bufs(ddcc_batch* b, int mode) {
   r.TB = static_cast<S*>(b->T[w]);
   r.hist = static_cast<S*>(b->hist);
   r.psi = static_cast<const S*>(b->psi);
-  r.ct = static_cast<const S*>(b->ct);
+  r.wet = static_cast<const S*>(b->wet);
   return r;
 }
 
@@ -1144,18 +1163,6 @@ int batch_capture(ddcc_batch* b) {
   return DDCC_OK;
 }
 
-template <class S>
-int upload_fields(ddcc_batch* b, int i, const double* src, void* dst,
-                  int planes) {
-  std::vector<S> tmp((size_t)planes * b->n[i]);
-  for (size_t k = 0; k < tmp.size(); ++k) tmp[k] = S(src[k]);
-  int rc = copy_planes(b, i, dst, tmp.data(), planes, sizeof(S),
-                       hipMemcpyHostToDevice);
-  if (rc) return rc;
-  BHIP(b, hipStreamSynchronize(b->stream), "sync");
-  return DDCC_OK;
-}
-
 }  // namespace
 
 extern "C" {
@@ -1226,7 +1233,7 @@ int ddcc_batch_create(const ddcc_params* p, int count, const int* nx,
   }
   if (e == hipSuccess) e = hipMalloc(&b->hist, (size_t)nhist_of(N) * nt * b->esz);
   if (e == hipSuccess) e = hipMalloc(&b->psi, nt * b->esz);
-  if (e == hipSuccess) e = hipMalloc(&b->ct, (size_t)(N - 1) * nt * b->esz);
+  if (e == hipSuccess) e = hipMalloc(&b->wet, (size_t)(N - 1) * nt * b->esz);
   if (e == hipSuccess)
     e = hipMalloc(&b->staging, (size_t)(N + 3) * nt * sizeof(double));
   long long mb = (ntot + 255) / 256;
@@ -1262,22 +1269,34 @@ int ddcc_batch_init_geometry(ddcc_batch* b, int i, const double* psi,
   for (size_t k = 0; k < n; ++k)
     if (!(psi[k] >= 0.0 && psi[k] <= 1.0))
       return bfail(b, DDCC_E_INVAL, "psi outside [0, 1]");
-  std::vector<double> zeros;
-  if (ct) {
+  if (ct)
     for (size_t k = 0; k < (size_t)(N - 1) * n; ++k)
       if (!(ct[k] >= -1.0 && ct[k] <= 1.0))
         return bfail(b, DDCC_E_INVAL, "cos theta outside [-1, 1]");
-  } else {
-    zeros.assign((size_t)(N - 1) * n, 0.0);
-    ct = zeros.data();
-  }
-  const bool f64 = b->p.precision == DDCC_FP64;
-  rc = f64 ? upload_fields<double>(b, i, psi, b->psi, 1)
-           : upload_fields<float>(b, i, psi, b->psi, 1);
-  if (rc) return rc;
-  rc = f64 ? upload_fields<double>(b, i, ct, b->ct, N - 1)
-           : upload_fields<float>(b, i, ct, b->ct, N - 1);
-  if (rc) return rc;
+  // psi and the wetting weights of the instance, computed on the device
+  const size_t nc = ct ? (size_t)(N - 1) * n : 0;
+  double* d = nullptr;
+  BHIP(b, hipMalloc(&d, (n + nc) * sizeof(double)), "hipMalloc geometry");
+  hipError_t e = hipMemcpyAsync(d, psi, n * sizeof(double),
+                                hipMemcpyHostToDevice, b->stream);
+  if (e == hipSuccess && nc)
+    e = hipMemcpyAsync(d + n, ct, nc * sizeof(double), hipMemcpyHostToDevice,
+                       b->stream);
+  if (e == hipSuccess)
+    e = b->p.precision == DDCC_FP64
+            ? launch_wet_field<double>(d, nc ? d + n : nullptr, 1, N - 1,
+                                       b->nx[i], b->ny[i], 1,
+                                       static_cast<double*>(b->psi),
+                                       static_cast<double*>(b->wet), b->ntot,
+                                       b->off[i], b->stream)
+            : launch_wet_field<float>(d, nc ? d + n : nullptr, 1, N - 1,
+                                      b->nx[i], b->ny[i], 1,
+                                      static_cast<float*>(b->psi),
+                                      static_cast<float*>(b->wet), b->ntot,
+                                      b->off[i], b->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+  (void)hipFree(d);
+  if (e != hipSuccess) return bhip(b, e, "batch geometry");
   b->geom_ok[i] = 1;
   b->fields_ok[i] = 0;
   return DDCC_OK;

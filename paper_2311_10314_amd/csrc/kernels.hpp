@@ -27,7 +27,9 @@ struct Bufs {
   const S* TA;
   S* TB;
   const S* psi;
-  const S* ct;
+  // wetting weights E_i = sum_k cos theta^k_iN |grad psi_k| over the walls,
+  // [N-1][n] (eqs. 2.9, 2.14; Section 4.5)
+  const S* wet;
   const double* inC;
   const double* inU;
   const double* inP;
@@ -55,10 +57,11 @@ hipError_t launch_2d(int nphase, int mode, const Coef<double>& kd,
                      const Coef<R>& k, const Bufs<Pop, S>& b, int ty,
                      hipStream_t st);
 
+// lattice_f: the phase-set lattice id (D3Q15 or D3Q7 of lattice.hpp).
 template <class Pop, class S, class R>
-hipError_t launch_3d(int nphase, int mode, const Coef<double>& kd,
-                     const Coef<R>& k, const Bufs<Pop, S>& b, int tx, int ty,
-                     hipStream_t st);
+hipError_t launch_3d(int nphase, int lattice_f, int mode,
+                     const Coef<double>& kd, const Coef<R>& k,
+                     const Bufs<Pop, S>& b, int tx, int ty, hipStream_t st);
 
 // Batches of independent 2D boxes: one work-queue entry per tile, and the
 // size and node offset of every instance. Each plane of each buffer holds
@@ -86,6 +89,18 @@ hipError_t launch_2d_batch(int nphase, int mode, const Coef<double>& kd,
 // Resident workgroups per compute unit of the batch kernel (0 on error).
 template <class Pop, class S, class R>
 int batch_blocks_per_cu(int nphase, int ty);
+
+// Geometry from K walls: psi = prod_k psi_k and the wetting weights
+// E_i = sum_k cos theta^k_iN |grad psi_k| (i < N-1), the gradient by the
+// fixed isotropic stencil (D2Q9 at nz = 1, else D3Q19) on the periodic
+// nx x ny x nz box. Inputs float64 on the device: psik [K][n], ctk
+// [K][N-1][n] (NULL: 90 degrees). Outputs in S at node off + x of planes of
+// plane_stride nodes.
+template <class S>
+hipError_t launch_wet_field(const double* psik, const double* ctk, int K,
+                            int nm1, int nx, int ny, int nz, S* psi_out,
+                            S* wet_out, long long plane_stride, long long off,
+                            hipStream_t st);
 
 // dst[i] = v for i < count (a kernel, so that it can sit in a captured graph).
 hipError_t launch_fill_u32(unsigned* dst, unsigned v, long long count,

@@ -6,7 +6,8 @@
 //   phase 1  pull f^i from buffer A and sum: phi C_i, C_i = phi C_i / psi_hat
 //            on the tile plus a 2-node halo, into LDS with psi and phi rho;
 //   phase 2  chemical potential phi mu_i (eq. 2.14) on the tile plus a
-//            1-node halo (needs div(psi grad C_j) and |grad psi| from LDS),
+//            1-node halo (needs div(psi grad C_j) from LDS and the static
+//            wetting weights sum_k cos theta^k_iN |grad psi_k|),
 //            mu_i = phi mu_i / psi_hat into LDS, and the lagged flux tensor T;
 //   phase 3  own node: gradients from LDS, mobility terms (eqs. 2.5, 3.7),
 //            force and velocity (eq. 3.13 with the implicit penalty),
@@ -225,8 +226,6 @@ struct Step2D {
     const Patch<D> ps = patch(sm.psi, lx, ly);
     const D psi = ps.v[1][1];
     const D psih = psi > k.psi_min ? psi : k.psi_min;
-    const D gpx = grad_x(ps), gpy = grad_y(ps);
-    const D agp = sqrt(gpx * gpx + gpy * gpy);
     D C[N], L[N];
 #pragma unroll
     for (int j = 0; j < N; ++j) {
@@ -234,12 +233,13 @@ struct Step2D {
       C[j] = cp.v[1][1];
       L[j] = div_psi_grad(ps, cp);
     }
-    // cos theta_jq from the N-1 stored cos theta_iN (eq. 2.9)
+    // wetting weights sum_k cos theta^k_jq |grad psi_k| from the stored
+    // E_i = sum_k cos theta^k_iN |grad psi_k| (eq. 2.9 is linear in them)
     D ct[N];
 #pragma unroll
-    for (int i = 0; i < N - 1; ++i) ct[i] = D(ldp(b.ct + (long long)(i) * gd.n, idx));
+    for (int i = 0; i < N - 1; ++i) ct[i] = D(ldp(b.wet + (long long)(i) * gd.n, idx));
     ct[N - 1] = D(0);
-    D W[N];  // sum_{q != j} cos theta_jq C_j C_q
+    D W[N];  // sum_{q != j} (sum_k cos theta^k_jq |grad psi_k|) C_j C_q
 #pragma unroll
     for (int j = 0; j < N; ++j) {
       D acc = D(0);
@@ -263,7 +263,7 @@ struct Step2D {
           wet += k.wet3[i][j] * W[j];
         }
       }
-      const D pm = psi * bulk + grad + wet * agp;
+      const D pm = psi * bulk + grad + wet;
       psimu_out[i] = pm;
       sm.mu[i][my][mx] = pm / psih;
     }

@@ -1,12 +1,12 @@
-// 3D DD-CCLB step for gfx950: D3Q15 phase sets, D3Q19 flow set.
+// 3D DD-CCLB step for gfx950: D3Q15 or D3Q7 phase sets, D3Q19 flow set.
 //
 // A step is three kernels on one stream, each one node per thread with no
 // workgroup barriers, so that occupancy is set by registers alone:
 //   k_frac3d  pull the phase populations and sum them: phi C_i, then
 //             C_i = phi C_i / sum_j phi C_j, written as a float64 field;
 //   k_mu3d    phi mu_i (eq. 2.14) from C_j and psi on the 18 D3Q19
-//             neighbours (div(psi grad C_j), |grad psi|), mu_i = phi mu_i /
-//             psi_hat written as a float64 field;
+//             neighbours (div(psi grad C_j)) and the static wetting weights,
+//             mu_i = phi mu_i / psi_hat written as a float64 field;
 //   k_step3d  gradients of C_i, mu_i, psi and psi rho and the divergence of
 //             the lagged flux tensor T from the neighbours, mobility terms
 //             (eqs. 2.5, 3.7), force and implicit-penalty velocity (eq.
@@ -188,8 +188,6 @@ __global__ __launch_bounds__(TX* TY) void k_mu3d(Coef<double> k, Bufs<Pop, S> b)
   const Star<D> ps = gather<D>(b.psi, nb);
   const D psi = ps.v[0];
   const D psih = psi > k.psi_min ? psi : k.psi_min;
-  const D g0 = sgrad<0>(ps), g1 = sgrad<1>(ps), g2 = sgrad<2>(ps);
-  const D agp = sqrt(g0 * g0 + g1 * g1 + g2 * g2);
   D C[N], L[N];
 #pragma unroll
   for (int j = 0; j < N; ++j) {
@@ -197,12 +195,13 @@ __global__ __launch_bounds__(TX* TY) void k_mu3d(Coef<double> k, Bufs<Pop, S> b)
     C[j] = cs.v[0];
     L[j] = sdiv_psi_grad(ps, cs);
   }
-  // cos theta_jq from the N-1 stored cos theta_iN (eq. 2.9)
+  // wetting weights sum_k cos theta^k_jq |grad psi_k| from the stored
+  // E_i = sum_k cos theta^k_iN |grad psi_k| (eq. 2.9 is linear in them)
   D ct[N];
 #pragma unroll
-  for (int i = 0; i < N - 1; ++i) ct[i] = D(ldp(b.ct + (long long)i * k.n, idx));
+  for (int i = 0; i < N - 1; ++i) ct[i] = D(ldp(b.wet + (long long)i * k.n, idx));
   ct[N - 1] = D(0);
-  D W[N];  // sum_{q != j} cos theta_jq C_j C_q
+  D W[N];  // sum_{q != j} (sum_k cos theta^k_jq |grad psi_k|) C_j C_q
 #pragma unroll
   for (int j = 0; j < N; ++j) {
     D acc = D(0);
@@ -225,7 +224,7 @@ __global__ __launch_bounds__(TX* TY) void k_mu3d(Coef<double> k, Bufs<Pop, S> b)
         grad += k.grad34[i][j] * L[j];
         wet += k.wet3[i][j] * W[j];
       }
-    stp(b.fmu + (long long)i * k.n, idx, (psi * bulk + grad + wet * agp) / psih);
+    stp(b.fmu + (long long)i * k.n, idx, (psi * bulk + grad + wet) / psih);
   }
 }
 
@@ -501,71 +500,76 @@ __global__ __launch_bounds__(TX* TY) void k_step3d(Coef<double> kd, Coef<R> k,
   for (int c = 0; c < 3; ++c) stp(b.TB + (long long)c * n, idx, S(Tn[c]));
 }
 
-template <int N, class Pop, class S, class R, int MODE, int TY>
+template <int N, class LF, class Pop, class S, class R, int MODE, int TY>
 hipError_t launch_3(const Coef<double>& kd, const Coef<R>& k,
                     const Bufs<Pop, S>& b, hipStream_t st) {
   const dim3 g((k.nx + TX - 1) / TX, (k.ny + TY - 1) / TY, k.nz);
   const dim3 blk(TX * TY);
-  hipLaunchKernelGGL((k_frac3d<N, D3Q15, Pop, S, R, MODE, TY>), g, blk, 0, st, kd, b);
+  hipLaunchKernelGGL((k_frac3d<N, LF, Pop, S, R, MODE, TY>), g, blk, 0, st, kd, b);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_mu3d<N, Pop, S, TY>), g, blk, 0, st, kd, b);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_step3d<N, D3Q15, D3Q19, Pop, S, R, MODE, TY>), g, blk, 0, st,
+  hipLaunchKernelGGL((k_step3d<N, LF, D3Q19, Pop, S, R, MODE, TY>), g, blk, 0, st,
                      kd, k, b);
   return hipGetLastError();
 }
 
 template <int N, class Pop, class S, class R, int MODE>
-hipError_t launch_ty3(const Coef<double>& kd, const Coef<R>& k,
+hipError_t launch_ty3(int lattice_f, const Coef<double>& kd, const Coef<R>& k,
                       const Bufs<Pop, S>& b, int ty, hipStream_t st) {
-  if (ty == 2) return launch_3<N, Pop, S, R, MODE, 2>(kd, k, b, st);
-  return launch_3<N, Pop, S, R, MODE, 4>(kd, k, b, st);
+  if (lattice_f == D3Q7::ID) {
+    if (ty == 2) return launch_3<N, D3Q7, Pop, S, R, MODE, 2>(kd, k, b, st);
+    return launch_3<N, D3Q7, Pop, S, R, MODE, 4>(kd, k, b, st);
+  }
+  if (ty == 2) return launch_3<N, D3Q15, Pop, S, R, MODE, 2>(kd, k, b, st);
+  return launch_3<N, D3Q15, Pop, S, R, MODE, 4>(kd, k, b, st);
 }
 
 template <int N, class Pop, class S, class R>
-hipError_t launch_mode3(int mode, const Coef<double>& kd, const Coef<R>& k,
-                        const Bufs<Pop, S>& b, int ty, hipStream_t st) {
+hipError_t launch_mode3(int mode, int lattice_f, const Coef<double>& kd,
+                        const Coef<R>& k, const Bufs<Pop, S>& b, int ty,
+                        hipStream_t st) {
   switch (mode) {
     case MODE_STEP:
-      return launch_ty3<N, Pop, S, R, MODE_STEP>(kd, k, b, ty, st);
+      return launch_ty3<N, Pop, S, R, MODE_STEP>(lattice_f, kd, k, b, ty, st);
     case MODE_INIT:
-      return launch_ty3<N, Pop, S, R, MODE_INIT>(kd, k, b, ty, st);
+      return launch_ty3<N, Pop, S, R, MODE_INIT>(lattice_f, kd, k, b, ty, st);
     default:
-      return launch_ty3<N, Pop, S, R, MODE_MOMENTS>(kd, k, b, ty, st);
+      return launch_ty3<N, Pop, S, R, MODE_MOMENTS>(lattice_f, kd, k, b, ty, st);
   }
 }
 
 }  // namespace
 
 template <class Pop, class S, class R>
-hipError_t launch_3d(int nphase, int mode, const Coef<double>& kd,
-                     const Coef<R>& k, const Bufs<Pop, S>& b, int tx, int ty,
-                     hipStream_t st) {
+hipError_t launch_3d(int nphase, int lattice_f, int mode,
+                     const Coef<double>& kd, const Coef<R>& k,
+                     const Bufs<Pop, S>& b, int tx, int ty, hipStream_t st) {
   (void)tx;
   if (!b.fC || !b.fmu) return hipErrorInvalidValue;
   switch (nphase) {
     case 2:
-      return launch_mode3<2, Pop, S, R>(mode, kd, k, b, ty, st);
+      return launch_mode3<2, Pop, S, R>(mode, lattice_f, kd, k, b, ty, st);
     case 3:
-      return launch_mode3<3, Pop, S, R>(mode, kd, k, b, ty, st);
+      return launch_mode3<3, Pop, S, R>(mode, lattice_f, kd, k, b, ty, st);
     default:
       return hipErrorInvalidValue;
   }
 }
 
 template hipError_t launch_3d<double, double, double>(
-    int, int, const Coef<double>&, const Coef<double>&,
+    int, int, int, const Coef<double>&, const Coef<double>&,
     const Bufs<double, double>&, int, int, hipStream_t);
 template hipError_t launch_3d<float, float, float>(
-    int, int, const Coef<double>&, const Coef<float>&,
+    int, int, int, const Coef<double>&, const Coef<float>&,
     const Bufs<float, float>&, int, int, hipStream_t);
 template hipError_t launch_3d<_Float16, float, float>(
-    int, int, const Coef<double>&, const Coef<float>&,
+    int, int, int, const Coef<double>&, const Coef<float>&,
     const Bufs<_Float16, float>&, int, int, hipStream_t);
 template hipError_t launch_3d<__bf16, float, float>(
-    int, int, const Coef<double>&, const Coef<float>&,
+    int, int, int, const Coef<double>&, const Coef<float>&,
     const Bufs<__bf16, float>&, int, int, hipStream_t);
 
 }  // namespace ddcc

@@ -73,7 +73,71 @@ __global__ void k_fill_u32(unsigned* dst, unsigned v, long long count) {
   if (i < count) dst[i] = v;
 }
 
+// Wetting weights of K walls (see launch_wet_field). One node per thread.
+template <class S>
+__global__ void k_wet_field(const double* psik, const double* ctk, int K,
+                            int nm1, int nx, int ny, int nz, S* psi_out,
+                            S* wet_out, long long stride, long long off) {
+  const long long n = (long long)nx * ny * nz;
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n) return;
+  const int x = int(idx % nx);
+  const int y = int((idx / nx) % ny);
+  const int z = int(idx / ((long long)nx * ny));
+  double ps = 1.0;
+  double E[kMaxN - 1] = {0.0, 0.0, 0.0};
+  for (int kk = 0; kk < K; ++kk) {
+    const double* p = psik + kk * n;
+    ps *= p[idx];
+    double g[3] = {0.0, 0.0, 0.0};
+    // isotropic stencil: D2Q9 (1/3 axes, 1/12 diagonals) or D3Q19 (1/6
+    // faces, 1/12 edges) weights at d0 = 1/3 over c_s^2 = 1/3
+    for (int dz = (nz > 1 ? -1 : 0); dz <= (nz > 1 ? 1 : 0); ++dz)
+      for (int dy = -1; dy <= 1; ++dy)
+        for (int dx = -1; dx <= 1; ++dx) {
+          const int m = dx * dx + dy * dy + dz * dz;
+          if (m == 0 || (nz > 1 && m == 3)) continue;
+          const double w = nz > 1 ? (m == 1 ? 1.0 / 6.0 : 1.0 / 12.0)
+                                  : (m == 1 ? 1.0 / 3.0 : 1.0 / 12.0);
+          const int xs = (x + dx + nx) % nx, ys = (y + dy + ny) % ny;
+          const int zs = nz > 1 ? (z + dz + nz) % nz : 0;
+          const double v = p[((long long)zs * ny + ys) * nx + xs];
+          g[0] += w * dx * v;
+          g[1] += w * dy * v;
+          g[2] += w * dz * v;
+        }
+    const double ag = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
+    for (int i = 0; i < nm1; ++i) {
+      const double c = ctk ? ctk[((long long)kk * nm1 + i) * n + idx] : 0.0;
+      E[i] += c * ag;
+    }
+  }
+  psi_out[off + idx] = S(ps);
+  for (int i = 0; i < nm1; ++i) wet_out[i * stride + off + idx] = S(E[i]);
+}
+
 }  // namespace
+
+template <class S>
+hipError_t launch_wet_field(const double* psik, const double* ctk, int K,
+                            int nm1, int nx, int ny, int nz, S* psi_out,
+                            S* wet_out, long long plane_stride, long long off,
+                            hipStream_t st) {
+  const long long n = (long long)nx * ny * nz;
+  if (n <= 0 || K < 1 || nm1 < 0 || nm1 > kMaxN - 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_wet_field<S>), dim3((unsigned)((n + 255) / 256)),
+                     dim3(256), 0, st, psik, ctk, K, nm1, nx, ny, nz, psi_out,
+                     wet_out, plane_stride, off);
+  return hipGetLastError();
+}
+
+template hipError_t launch_wet_field<double>(const double*, const double*, int,
+                                             int, int, int, int, double*,
+                                             double*, long long, long long,
+                                             hipStream_t);
+template hipError_t launch_wet_field<float>(const double*, const double*, int,
+                                            int, int, int, int, float*, float*,
+                                            long long, long long, hipStream_t);
 
 hipError_t launch_fill_u32(unsigned* dst, unsigned v, long long count,
                            hipStream_t st) {

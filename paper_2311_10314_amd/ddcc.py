@@ -71,6 +71,8 @@ def _load():
         "ddcc_create": (ctypes.c_int, [P(ddcc_params), vp, P(vp)]),
         "ddcc_init_geometry": (ctypes.c_int, [ctx, dp, dp]),
         "ddcc_init_geometry_dev": (ctypes.c_int, [ctx, vp, vp]),
+        "ddcc_init_geometry_walls": (ctypes.c_int, [ctx, ctypes.c_int, dp,
+                                                    dp]),
         "ddcc_init_fields": (ctypes.c_int, [ctx, dp, dp, dp]),
         "ddcc_init_fields_dev": (ctypes.c_int, [ctx, vp, vp, vp]),
         "ddcc_step": (ctypes.c_int, [ctx, ctypes.c_int64]),
@@ -118,6 +120,7 @@ ddcc_default_params = LIB.ddcc_default_params
 ddcc_create = LIB.ddcc_create
 ddcc_init_geometry = LIB.ddcc_init_geometry
 ddcc_init_geometry_dev = LIB.ddcc_init_geometry_dev
+ddcc_init_geometry_walls = LIB.ddcc_init_geometry_walls
 ddcc_init_fields = LIB.ddcc_init_fields
 ddcc_init_fields_dev = LIB.ddcc_init_fields_dev
 ddcc_step = LIB.ddcc_step
@@ -229,7 +232,11 @@ class Sim:
         p = make_params(wl.dim, wl.shape, wl.nphase, wl.lattice_f,
                         wl.lattice_g, precision, **wl.params)
         s = cls(p, stream)
-        s.init_geometry(wl.psi, wl.cos_theta_iN)
+        if getattr(wl, "walls", None):
+            s.init_geometry_walls([w[0] for w in wl.walls],
+                                  [w[1] for w in wl.walls])
+        else:
+            s.init_geometry(wl.psi, wl.cos_theta_iN)
         s.init_fields(wl.C0, wl.u0, wl.P0)
         return s
 
@@ -250,6 +257,14 @@ class Sim:
         self._check(LIB.ddcc_init_fields(
             self._h, _dptr(C), None if u is None else _dptr(u),
             None if P is None else _dptr(P)))
+
+    def init_geometry_walls(self, psis, cos_thetas=None):
+        """psis: K arrays psi_k; cos_thetas: K arrays cos theta^k_iN (or
+        None for 90 degrees)."""
+        psi = _c64(np.stack(psis))
+        ct = None if cos_thetas is None else _c64(np.stack(cos_thetas))
+        self._check(LIB.ddcc_init_geometry_walls(
+            self._h, len(psis), _dptr(psi), None if ct is None else _dptr(ct)))
 
     def init_geometry_dev(self, psi, cos_theta=None):
         self._check(LIB.ddcc_init_geometry_dev(
@@ -459,6 +474,8 @@ def unpack_state(sim, buf):
 VELOCITIES = {
     0: [(0, 0), (1, 0), (0, 1), (-1, 0), (0, -1), (1, 1), (-1, 1), (-1, -1),
         (1, -1)],
+    1: [(0, 0, 0), (1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1),
+        (0, 0, -1)],
     2: [(0, 0, 0), (1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1),
         (0, 0, -1), (1, 1, 1), (1, 1, -1), (1, -1, 1), (1, -1, -1),
         (-1, 1, 1), (-1, 1, -1), (-1, -1, 1), (-1, -1, -1)],

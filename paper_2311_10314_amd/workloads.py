@@ -213,21 +213,27 @@ def droplet_impact_sphere_3d(n=256, steps=5000):
 
 
 def wavy_channel_2d(n=256, theta_bottom=(120.0, 60.0), theta_top=(120.0, 60.0),
-                    amplitude=None, steps=2000):
+                    amplitude=None, thick=None, steps=2000):
     """2D, N = 3, two walls with their own wetting angles (Section 4.5): the
     bottom wall y = n/4 + B(x) and the top wall y = 3n/4 - B(x) of a
     periodic wavy channel, B(x) = 0.05 n sin(4 pi x / n) (the paper's
-    sqrt-modulated profile is not periodic), each wall its own smooth
-    characteristic function psi_k and angles (theta^k_13, theta^k_23); a
-    compound droplet (inner phase 1 of radius n/10, outer phase 2 of radius
-    n/6, phase 3 around) at the channel centre, pushed along x by a body
-    force density. Returns the walls in `walls` (psi_k, cos theta^k_iN)."""
+    sqrt-modulated profile is not periodic). Each wall is a solid band
+    `thick` cells thick (default n/6) behind its face, with its own smooth
+    characteristic function psi_k and angles (theta^k_13, theta^k_23); the
+    bands leave fluid on both sides (a second channel across the periodic
+    boundary), so that every psi_k is smooth on the periodic box by itself.
+    A compound droplet (inner phase 1 of radius n/10, outer phase 2 of radius
+    n/6, phase 3 around) sits at the channel centre, pushed along x by a body
+    force density. The walls are in `walls` as (psi_k, cos theta^k_iN)."""
     shape = (n, n)
     x, y = _grid(shape)
     A = 0.05 * n if amplitude is None else amplitude
+    w = n / 6.0 if thick is None else thick
     B = A * np.sin(4.0 * math.pi * x / n)
-    psi1 = psi_from_distance(y - (n / 4.0 + B))
-    psi2 = psi_from_distance((3.0 * n / 4.0 - B) - y)
+    c1 = n / 4.0 + B - w / 2.0           # band 1 ends at the bottom wall
+    c2 = 3.0 * n / 4.0 - B + w / 2.0     # band 2 starts at the top wall
+    psi1 = psi_from_distance(np.abs(_periodic_delta(y, c1, n)) - w / 2.0)
+    psi2 = psi_from_distance(np.abs(_periodic_delta(y, c2, n)) - w / 2.0)
     walls = []
     for psi_k, th in ((psi1, theta_bottom), (psi2, theta_top)):
         ct = np.stack([np.full(shape, math.cos(math.radians(t))) for t in th])

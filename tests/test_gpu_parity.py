@@ -166,3 +166,19 @@ def test_porous_reduced_100_steps(precision, tol):
     g = gpu_run(wl, 100, precision)
     e = _report("porous256 %s" % precision, g, o)
     assert e["C"] < tol and e["u"] < tol
+
+
+# ---- several walls with their own angles (Section 4.5) --------------------
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 1e-5)])
+def test_two_wall_channel(precision, tol):
+    """Wavy channel with two walls, each its own psi_k and angles, N = 3
+    compound droplet: the library's static wetting weights sum_k cos
+    theta^k_iN |grad psi_k| against the oracle's per-wall sum."""
+    wl = W.wavy_channel_2d(n=96, theta_bottom=(120.0, 60.0),
+                           theta_top=(60.0, 120.0))
+    o = oracle_run(wl, 100)
+    g = gpu_run(wl, 100, precision)
+    e = _report("two walls %s 100 steps" % precision, g, o)
+    assert e["C"] < tol and e["u"] < tol
+    drift = np.abs(g["mass"] - g["mass0"]) / np.abs(g["mass0"])
+    assert drift.max() < (1e-12 if precision == "fp64" else 1e-6)

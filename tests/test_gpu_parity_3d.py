@@ -126,3 +126,40 @@ def test_sphere_droplet_64_one_step(precision, tol):
     print("sphere64 %s one step: C %.2e u %.2e P %.2e f %.2e g %.2e" % (
         precision, eC, eu, eP, ef, eg), flush=True)
     assert max(eC, eu, ef, eg) < tol and eP < 100 * tol
+
+
+# ---- D3Q7 phase sets (the paper's own 3D phase lattice) -------------------
+def _d3q7_case(seed=21):
+    return W.random_small(3, 2, (10, 12, 66), seed=seed, lattice_f="D3Q7",
+                          d0=0.3)
+
+
+def test_d3q7_one_step_fp64():
+    """D3Q7 phase sets with the D3Q19 flow set, d0 = 0.3: one step of the
+    populations and 30 steps of the moments against the oracle."""
+    from paper_2311_10314_amd.ddcc import Sim
+    import oracle
+    wl = _d3q7_case()
+    sim = Sim.from_workload(wl, "fp64")
+    st = gpu_state_to_oracle(wl, sim)
+    prm, geo, _ = oracle.from_workload(wl)
+    st1 = oracle.step(prm, geo, st)
+    sim.step(1)
+    g1 = gpu_state_to_oracle(wl, sim)
+    ef = np.abs(g1.f - st1.f).max() / np.abs(st1.f).max()
+    eg = np.abs(g1.g - st1.g).max() / np.abs(st1.g).max()
+    print("d3q7 one step f %.2e g %.2e" % (ef, eg), flush=True)
+    assert ef < 1e-13 and eg < 1e-13
+    sim.close()
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 1e-4)])
+def test_d3q7_short_run(precision, tol):
+    wl = _d3q7_case(22)
+    o = oracle_run(wl, 30)
+    g = gpu_run(wl, 30, precision)
+    e = _err(g, o)
+    print("d3q7 %s 30 steps" % precision, e, flush=True)
+    assert e["C"] < tol and e["u"] < tol
+    drift = np.abs(g["mass"] - g["mass0"]) / np.abs(g["mass0"])
+    assert drift.max() < (1e-12 if precision == "fp64" else 1e-6)
