@@ -184,6 +184,75 @@ def copy_calibration(torch, mib=1024):
           flush=True)
 
 
+STEP_KERNEL = {"fp32": "float, float, float", "fp64": "double, double, double"}
+
+
+def _counter_means(csv_path, counter, precision, nphase):
+    """Mean counter value (KiB per dispatch) of the step kernel and of the
+    1 GiB calibration copy (the largest buffer-copy dispatch) in one
+    rocprofv3 counter run."""
+    import csv
+    step, copy = [], []
+    tag = "k_step2d<%d, %s, 0, " % (nphase, STEP_KERNEL[precision])
+    with open(csv_path) as fh:
+        rows = [r for r in csv.DictReader(fh) if r["Counter_Name"] == counter]
+    for r in rows:
+        if tag in r["Kernel_Name"]:
+            step.append(float(r["Counter_Value"]))
+    copies = [r for r in rows if "copyBuffer" in r["Kernel_Name"]]
+    if copies:
+        big = max(int(r["Grid_Size"]) for r in copies)
+        copy = [float(r["Counter_Value"]) for r in copies
+                if int(r["Grid_Size"]) == big]
+    if not step or not copy or max(copy) < 1.0e5:
+        raise SystemExit("%s: no %s dispatches of the step kernel or of the "
+                         "1 GiB copy (run with --copy-calibration)"
+                         % (csv_path, counter))
+    return sum(step) / len(step), sum(copy) / len(copy), len(step)
+
+
+def traffic_summary(fetch_dir, write_dir, precision, n):
+    """Scale the FETCH_SIZE and WRITE_SIZE counters of the step kernel by
+    what they read for a 1 GiB device copy in the same run, and record the
+    HBM bytes per launch in profiles/hbm_traffic.json under the hash of the
+    kernel sources (bench.py reports them only while the hash matches)."""
+    wl = make_workload(n)
+    N = wl.nphase
+    f_step, f_copy, nd = _counter_means(
+        os.path.join(fetch_dir, "run_counter_collection.csv"), "FETCH_SIZE",
+        precision, N)
+    w_step, w_copy, _ = _counter_means(
+        os.path.join(write_dir, "run_counter_collection.csv"), "WRITE_SIZE",
+        precision, N)
+    gib_kib = 1024.0 * 1024.0
+    ff, wf = gib_kib / f_copy, gib_kib / w_copy
+    per_launch = (f_step * ff + w_step * wf) * 1024.0
+    entry = {"kernel": "k_step2d<%d, %s, 0, 8>" % (N, STEP_KERNEL[precision]),
+             "workload": "porous_bands_2d %dx%d N=%d" % (n, n, N),
+             "kernel_hash": kernel_source_hash(),
+             "dispatches": nd,
+             "fetch_kib_per_dispatch": f_step,
+             "write_kib_per_dispatch": w_step,
+             "copy_fetch_kib_for_1GiB": f_copy,
+             "copy_write_kib_for_1GiB": w_copy,
+             "fetch_factor": ff, "write_factor": wf,
+             "read_bytes_per_launch": f_step * ff * 1024.0,
+             "write_bytes_per_launch": w_step * wf * 1024.0,
+             "bytes_per_launch": per_launch,
+             "algorithmic_bytes_per_launch":
+                 algorithmic_bytes_per_node(N, 2, 9, 9, precision) * wl.nodes}
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        t = {}
+    t[precision] = entry
+    with open(TRAFFIC_FILE, "w") as fh:
+        json.dump(t, fh, indent=1)
+        fh.write("\n")
+    print(json.dumps(entry, indent=1))
+
+
 def time_gpu(wl, precision, steps, warmup, torch, tile=0):
     from paper_2311_10314_amd.ddcc import Sim
     stream = torch.cuda.Stream()
@@ -270,9 +339,17 @@ def main():
                     help="also time this many batched instances (0: skip)")
     ap.add_argument("--batch-steps", type=int, default=200)
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--traffic-summary", nargs=2, metavar=("FETCH_DIR",
+                                                           "WRITE_DIR"),
+                    help="write profiles/hbm_traffic.json from two "
+                         "rocprofv3 counter runs (no GPU needed)")
     ap.add_argument("--precision", default="both",
                     choices=["both", "fp32", "fp64"])
     a = ap.parse_args()
+    if a.traffic_summary:
+        traffic_summary(a.traffic_summary[0], a.traffic_summary[1],
+                        "fp64" if a.precision == "fp64" else "fp32", a.n)
+        return 0
     if a.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU "
               "path (see the design notes for how the grid would shard)",

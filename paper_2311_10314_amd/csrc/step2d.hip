@@ -272,12 +272,29 @@ struct Step2D {
 
   __device__ static void run(const Coef<D>& kd, const Coef<R>& k,
                              const Bufs<Pop, S>& b) {
-    // Natural tile order: workgroups go to the 8 XCDs round-robin, so with
-    // a multiple of 8 tiles per row the tiles above and below (which share
-    // halo rows) run on the same XCD and the whole chip sweeps one band of
-    // rows at a time.
+    // Tile order. Workgroup w is dispatched to XCD w % 8. The row-major tile
+    // list is cut into spans of 8 chunks of CH full-width tile rows (64 node
+    // rows), and inside a span each XCD takes one contiguous range, about one
+    // chunk. The halo lines shared by neighbouring tiles (left, right and
+    // below) then sit in one XCD's L2 instead of being fetched by two or
+    // three, and the eight XCDs work on adjacent chunks, so the pages in use
+    // stay few.
     __shared__ Smem sm;
-    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
+    int x0, y0;
+    {
+      constexpr unsigned CH = TY >= 64 ? 1u : 64u / TY;
+      const unsigned gx = gridDim.x, total = gx * gridDim.y;
+      const unsigned lin = blockIdx.y * gx + blockIdx.x;
+      const unsigned span = 8u * CH * gx;
+      const unsigned base = lin / span * span;
+      const unsigned m = min(span, total - base);
+      const unsigned l = lin - base, q = m / 8u, r = m % 8u;
+      const unsigned xc = l % 8u, j = l / 8u;
+      const unsigned t = base + (xc < r ? xc * (q + 1u) + j
+                                        : r * (q + 1u) + (xc - r) * q + j);
+      x0 = int(t % gx) * TX;
+      y0 = int(t / gx) * TY;
+    }
     const int tid = threadIdx.x;
     const int tx = tid % TX, ty = tid / TX;
     D psiC[N], psimu_d[N], dummy[N];
