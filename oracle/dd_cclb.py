@@ -35,6 +35,75 @@ RATE_KEYS = ("0", "1", "21", "22", "3", "4")
 
 
 # --------------------------------------------------------------------------
+# Array helpers. The grid functions below take numpy float64 arrays; they
+# also take torch float64 CPU tensors, with the same arithmetic, so that
+# oracle.adjoint can differentiate this very step by reverse-mode automatic
+# differentiation. Constants (lattice tables, parameters) stay numpy.
+# --------------------------------------------------------------------------
+def _is_torch(a):
+    return type(a).__module__.split(".")[0] == "torch"
+
+
+def zeros(shape, like):
+    """float64 zeros of `shape`, a torch tensor if `like` is one."""
+    if _is_torch(like):
+        return like.new_zeros(tuple(int(v) for v in shape))
+    return np.zeros(shape)
+
+
+def stack(arrays):
+    arrays = list(arrays)
+    if _is_torch(arrays[0]):
+        import torch
+        return torch.stack(arrays)
+    return np.array(arrays)
+
+
+def as_f64(a):
+    """A float64 grid array: torch tensors pass through, the rest goes to
+    numpy."""
+    return a if _is_torch(a) else np.array(a, dtype=np.float64)
+
+
+def _roll(a, shift, axis):
+    if _is_torch(a):
+        import torch
+        return torch.roll(a, shift, dims=axis)
+    return np.roll(a, shift, axis=axis)
+
+
+def floor_at(a, m):
+    """max(a, m) elementwise."""
+    if _is_torch(a):
+        import torch
+        return torch.clamp(a, min=m)
+    return np.maximum(a, m)
+
+
+def vector_norm(v):
+    """|v| over the first axis. Its derivative at v = 0 is taken as 0 (the
+    torch path guards the square root there)."""
+    s = (v ** 2).sum(axis=0)
+    if _is_torch(v):
+        import torch
+        pos = s > 0
+        return torch.where(pos, torch.sqrt(torch.where(pos, s,
+                                                       torch.ones_like(s))),
+                           torch.zeros_like(s))
+    return np.sqrt(s)
+
+
+def _apply(mat, x):
+    """sum_q mat[k, q] x[q] for a constant (Q, Q) matrix and x of shape
+    (Q,) + grid."""
+    if _is_torch(x):
+        import torch
+        return torch.tensordot(torch.as_tensor(mat, dtype=x.dtype), x,
+                               dims=([1], [0]))
+    return np.tensordot(mat, x, axes=(1, 0))
+
+
+# --------------------------------------------------------------------------
 # Parameters
 # --------------------------------------------------------------------------
 class Params:
@@ -110,7 +179,7 @@ def shifted(field, c):
     out = field
     for a, ca in enumerate(c):
         if ca != 0:
-            out = np.roll(out, -int(ca), axis=-1 - a)
+            out = _roll(out, -int(ca), -1 - a)
     return out
 
 
@@ -118,7 +187,7 @@ def grad(field, d):
     """Central isotropic gradient: sum_p w_p c_p field(x + c_p) / c_s^2.
     Returns shape (d,) + field.shape."""
     cst, wst, cs2 = stencil_lattice(d)
-    out = np.zeros((d,) + field.shape)
+    out = zeros((d,) + tuple(field.shape), field)
     for p in range(1, len(wst)):
         fs = shifted(field, cst[p])
         for a in range(d):
@@ -131,7 +200,7 @@ def div_psi_grad(psi, C, d):
     """Conservative div(psi grad C), the term of eq. (2.14):
     sum_p w_p [psi(x + c_p) + psi(x)] [C(x + c_p) - C(x)] / c_s^2."""
     cst, wst, cs2 = stencil_lattice(d)
-    out = np.zeros(C.shape)
+    out = zeros(C.shape, C)
     for p in range(1, len(wst)):
         out += wst[p] * (shifted(psi, cst[p]) + psi) * (shifted(C, cst[p]) - C)
     return out / cs2
@@ -139,7 +208,7 @@ def div_psi_grad(psi, C, d):
 
 def div_tensor(T, d):
     """(div T)_b = sum_a d_a T_ab for T of shape (d, d) + grid."""
-    out = np.zeros((d,) + T.shape[2:])
+    out = zeros((d,) + tuple(T.shape[2:]), T)
     for b in range(d):
         out[b] = sum(grad(T[a, b], d)[a] for a in range(d))
     return out
@@ -153,12 +222,12 @@ def pair_cosines(prm, cos_theta_iN, shape):
     every pair i != j, from the N - 1 angles theta_iN measured against the
     N-th phase (its own entry cos th_NN is absent, sigma_NN = 0)."""
     N = prm.N
-    ct = np.zeros((N,) + shape)
+    cos_theta_iN = as_f64(cos_theta_iN)
+    ct = zeros((N,) + tuple(shape), cos_theta_iN)
     if N > 1:
-        ct[:N - 1] = np.array(cos_theta_iN, dtype=np.float64).reshape(
-            (N - 1,) + shape)
+        ct[:N - 1] = cos_theta_iN.reshape((N - 1,) + tuple(shape))
     sg = prm.sigma
-    out = np.zeros((N, N) + shape)
+    out = zeros((N, N) + tuple(shape), cos_theta_iN)
     for i in range(N):
         for j in range(N):
             if i != j:
@@ -180,21 +249,20 @@ class Geometry:
         d = prm.dim
         if walls is None:
             walls = [(psi, cos_theta_iN)]
-            self.psi = np.array(psi, dtype=np.float64)
+            self.psi = as_f64(psi)
         else:
-            self.psi = np.ones(np.shape(walls[0][0]))
-            for psi_k, _ in walls:
-                self.psi = self.psi * np.array(psi_k, dtype=np.float64)
+            self.psi = as_f64(walls[0][0])
+            for psi_k, _ in walls[1:]:
+                self.psi = self.psi * as_f64(psi_k)
         # Reading: division by psi uses psi_hat = max(psi, psi_min).
-        self.psi_hat = np.maximum(self.psi, prm.psi_min)
+        self.psi_hat = floor_at(self.psi, prm.psi_min)
         self.grad_psi = grad(self.psi, d)
-        self.abs_grad_psi = np.sqrt((self.grad_psi ** 2).sum(axis=0))
+        self.abs_grad_psi = vector_norm(self.grad_psi)
         self.walls = []
         for psi_k, ct_k in walls:
-            pk = np.array(psi_k, dtype=np.float64)
-            g = grad(pk, d)
+            g = grad(as_f64(psi_k), d)
             self.walls.append((pair_cosines(prm, ct_k, self.psi.shape),
-                               np.sqrt((g ** 2).sum(axis=0))))
+                               vector_norm(g)))
         self.cos_theta = self.walls[0][0]
 
 
@@ -212,19 +280,19 @@ def chemical_potential(prm, geo, C, L):
     summed over the walls (cos th^k_jq |grad psi_k|, Section 4.5)."""
     N = prm.N
     psi = geo.psi
-    out = np.zeros(C.shape)
+    out = zeros(C.shape, C)
     for i in range(N):
-        acc = np.zeros(psi.shape)
+        acc = zeros(psi.shape, C)
         for j in range(N):
             acc += 2.0 * prm.beta[i, j] * psi * (g_prime(C[i])
                                                  - g_prime(C[i] + C[j]))
         for j in range(N):
             acc += 0.75 * prm.eps * prm.sigma[i, j] * L[j]
-        total = np.zeros(psi.shape)
+        total = zeros(psi.shape, C)
         for cos_theta, abs_grad_psi_k in geo.walls:
-            wet = np.zeros(psi.shape)
+            wet = zeros(psi.shape, C)
             for j in range(N):
-                inner = np.zeros(psi.shape)
+                inner = zeros(psi.shape, C)
                 for q in range(N):
                     if q != j:
                         inner += cos_theta[j, q] * C[j] * C[q]
@@ -237,7 +305,7 @@ def chemical_potential(prm, geo, C, L):
 def mobility(prm, C):
     """eq. (2.5): M_ij = -m0 C_i C_j (i != j), M_ii = -sum_{j != i} M_ij."""
     N = prm.N
-    M = np.zeros((N, N) + C.shape[1:])
+    M = zeros((N, N) + tuple(C.shape[1:]), C)
     for i in range(N):
         for j in range(N):
             if i != j:
@@ -251,7 +319,7 @@ def source_vector(prm, psi, M, grad_mu):
     """eq. (3.7): S_i = (psi M_ii - psi m0)/m0 grad mu_i
                        + sum_{j != i} psi M_ij / m0 grad mu_j."""
     N = prm.N
-    S = np.zeros(grad_mu.shape)
+    S = zeros(grad_mu.shape, grad_mu)
     for i in range(N):
         S[i] = (psi * M[i, i] - psi * prm.m0) / prm.m0 * grad_mu[i]
         for j in range(N):
@@ -263,7 +331,7 @@ def source_vector(prm, psi, M, grad_mu):
 def mass_flux(prm, M, grad_mu):
     """Section 2.2: m^C = -sum_ij rho_i M_ij grad mu_j."""
     N = prm.N
-    out = np.zeros(grad_mu.shape[1:])
+    out = zeros(grad_mu.shape[1:], grad_mu)
     for i in range(N):
         for j in range(N):
             out -= prm.rho[i] * M[i, j] * grad_mu[j]
@@ -287,7 +355,7 @@ def hermite2_expansion(lat, A):
     Returns a (Q,) + grid array (without the weight w_p)."""
     cs2 = lat.cs2
     d = lat.d
-    out = np.zeros((lat.Q,) + A.shape[2:])
+    out = zeros((lat.Q,) + tuple(A.shape[2:]), A)
     for p in range(lat.Q):
         c = lat.c[p]
         for a in range(d):
@@ -302,7 +370,7 @@ def f_equilibrium(lat, psiC_i, psimu_i, X_i, eta_i):
     """eq. (3.5): p = 0: (w_0 - 1) eta phi mu + phi C;
                   p != 0: w_p eta phi mu + w_p c_p . (phi C u) / c_s^2."""
     cs2 = lat.cs2
-    out = np.zeros((lat.Q,) + psiC_i.shape)
+    out = zeros((lat.Q,) + tuple(psiC_i.shape), psiC_i)
     for p in range(lat.Q):
         cu = sum(lat.c[p][a] * X_i[a] for a in range(lat.d))
         if p == 0:
@@ -315,7 +383,7 @@ def f_equilibrium(lat, psiC_i, psimu_i, X_i, eta_i):
 def f_source(lat, V_i):
     """eq. (3.6): F^i_p = w_p c_p . V / c_s^2 with
     V = d_t(phi C_i u) + c_s^2 eta_i (mu_i grad phi - S_i)."""
-    out = np.zeros((lat.Q,) + V_i.shape[1:])
+    out = zeros((lat.Q,) + tuple(V_i.shape[1:]), V_i)
     for p in range(lat.Q):
         out[p] = lat.w[p] * sum(lat.c[p][a] * V_i[a]
                                 for a in range(lat.d)) / lat.cs2
@@ -329,12 +397,12 @@ def g_equilibrium(lat, psiP, rho0, psirho, u, Y):
     Y is the symmetric part (phi m^C u + phi u m^C)/2."""
     d = lat.d
     cs2 = lat.cs2
-    A = np.zeros((d, d) + psiP.shape)
+    A = zeros((d, d) + tuple(psiP.shape), psiP)
     for a in range(d):
         for b in range(d):
             A[a, b] = psirho * u[a] * u[b] + Y[a, b]
     h2 = hermite2_expansion(lat, A)
-    out = np.zeros((lat.Q,) + psiP.shape)
+    out = zeros((lat.Q,) + tuple(psiP.shape), psiP)
     for p in range(lat.Q):
         cj = sum(lat.c[p][a] * psirho * u[a] for a in range(d))
         s_p = lat.w[p] * (cj / cs2 + h2[p])
@@ -362,7 +430,7 @@ def m2g_tensor(lat, dtY, u, grad_psirho):
     d = lat.d
     cs2 = lat.cs2
     udotb = sum(u[a] * grad_psirho[a] for a in range(d))
-    M = np.zeros(dtY.shape)
+    M = zeros(dtY.shape, dtY)
     for a in range(d):
         for b in range(d):
             M[a, b] = dtY[a, b] + cs2 * (u[a] * grad_psirho[b]
@@ -377,7 +445,7 @@ def g_source(lat, psi, u, grad_rho, F, M2G):
     d = lat.d
     a0 = psi * sum(u[a] * grad_rho[a] for a in range(d))
     h2 = hermite2_expansion(lat, M2G)
-    out = np.zeros((lat.Q,) + psi.shape)
+    out = zeros((lat.Q,) + tuple(psi.shape), u)
     for p in range(lat.Q):
         cF = sum(lat.c[p][a] * F[a] for a in range(d))
         out[p] = lat.w[p] * (a0 + cF / lat.cs2 + h2[p])
@@ -387,18 +455,18 @@ def g_source(lat, psi, u, grad_rho, F, M2G):
 def collide(lat, pop, eq, src, rates):
     """eqs. (3.1)-(3.4): f* = f - Lambda (f - f^eq) + dt (I - Lambda/2) F with
     Lambda = H^-1 S H; S may vary per node (rates: list of Q scalars/arrays)."""
-    m_ne = np.tensordot(lat.H, pop - eq, axes=(1, 0))
-    m_src = np.tensordot(lat.H, src, axes=(1, 0))
-    mstar = np.empty_like(m_ne)
+    m_ne = _apply(lat.H, pop - eq)
+    m_src = _apply(lat.H, src)
+    mstar = zeros(m_ne.shape, m_ne)
     for k in range(lat.Q):
         s = rates[k]
         mstar[k] = s * m_ne[k] - (1.0 - 0.5 * s) * m_src[k]
-    return pop - np.tensordot(lat.Hinv, mstar, axes=(1, 0))
+    return pop - _apply(lat.Hinv, mstar)
 
 
 def stream(lat, post):
     """Pull streaming, periodic: f_p(x, t + dt) = f*_p(x - c_p, t)."""
-    out = np.empty_like(post)
+    out = zeros(post.shape, post)
     for p in range(lat.Q):
         out[p] = shifted(post[p], -lat.c[p])
     return out
@@ -432,17 +500,17 @@ def _phase_fields(prm, geo, psiC):
     # the divisor keeps the constraint exact on the lattice (without it the
     # bulk energy, which falls along sum_j C_j - 1, amplifies round-off) and
     # keeps C_i defined where phi underflows inside solids.
-    C = psiC / np.maximum(psiC.sum(axis=0), prm.psi_min)
+    C = psiC / floor_at(psiC.sum(axis=0), prm.psi_min)
     rho = sum(prm.rho[i] * C[i] for i in range(N))           # linear mixing
     nu = sum(prm.nu[i] * C[i] for i in range(N))
     psirho = psi * rho
-    gradC = np.array([grad(C[i], d) for i in range(N)])      # (N, d, grid)
-    L = np.array([div_psi_grad(psi, C[j], d) for j in range(N)])
+    gradC = stack([grad(C[i], d) for i in range(N)])         # (N, d, grid)
+    L = stack([div_psi_grad(psi, C[j], d) for j in range(N)])
     grad_rho = sum(prm.rho[i] * gradC[i] for i in range(N))
     grad_psirho = grad(psirho, d)
     psimu = chemical_potential(prm, geo, C, L)
     mu = psimu / geo.psi_hat
-    grad_mu = np.array([grad(mu[i], d) for i in range(N)])
+    grad_mu = stack([grad(mu[i], d) for i in range(N)])
     M = mobility(prm, C)
     S = source_vector(prm, psi, M, grad_mu)
     mC = mass_flux(prm, M, grad_mu)
@@ -453,8 +521,8 @@ def _phase_fields(prm, geo, psiC):
 
 def _tensors(psi, mC, u):
     d = u.shape[0]
-    Y = np.zeros((d, d) + psi.shape)
-    T = np.zeros((d, d) + psi.shape)
+    Y = zeros((d, d) + tuple(psi.shape), u)
+    T = zeros((d, d) + tuple(psi.shape), u)
     for a in range(d):
         for b in range(d):
             Y[a, b] = 0.5 * (psi * mC[a] * u[b] + psi * u[a] * mC[b])
@@ -472,8 +540,8 @@ def macroscopic(prm, geo, st):
     psiC = st.f.sum(axis=1)                                  # phi C_i = sum_p f^i_p
     q = _phase_fields(prm, geo, psiC)
     psirho = q["psirho"]
-    j = np.array([sum(lat_g.c[p][a] * st.g[p] for p in range(lat_g.Q))
-                  for a in range(d)])
+    j = stack([sum(lat_g.c[p][a] * st.g[p] for p in range(lat_g.Q))
+               for a in range(d)])
     sum_g_moving = st.g[1:].sum(axis=0)
     # eq. (3.13): F = -div T + sum_i phi mu_i grad C_i + P grad phi
     #               - (1 - phi) lam u, plus phi (rho a + G) for a body
@@ -523,7 +591,7 @@ def step(prm, geo, st):
     q = macroscopic(prm, geo, st)
     cs2 = prm.cs2
     rates_f = lat_f.rate_vector(prm.s_f)
-    f_new = np.empty_like(st.f)
+    f_new = zeros(st.f.shape, st.f)
     for i in range(N):
         feq = f_equilibrium(lat_f, q["psiC"][i], q["psimu"][i], q["X"][i],
                             prm.eta[i])
