@@ -171,6 +171,71 @@ def batched_leg(count, steps, torch, graph_steps=50):
     return out
 
 
+def adjoint_leg(n, steps, interval, torch):
+    """Adjoint sweep on the wavy channel (256 x 256, N = 2, per-node angle
+    field): wall time of ddcc_adjoint (forward sweep with checkpoints,
+    segment recomputation and the reverse sweep) against the forward steps
+    alone, in FP32 and FP64, with the FP32 gradient's deviation from the
+    FP64 one and the FP64 gradient against central differences along a
+    smooth random direction of the angle field."""
+    import numpy as np
+
+    from paper_2311_10314_amd import workloads as W
+    from paper_2311_10314_amd.ddcc import Sim
+    wl = W.adjoint_channel_2d(n=n, steps=steps)
+    out = {"workload": "adjoint_channel_2d %dx%d N=2, %d steps, checkpoints "
+                       "every %d" % (n, n, steps, interval)}
+    grads = {}
+    for prec in ("fp32", "fp64"):
+        sim = Sim.from_workload(wl, prec)
+        state = sim.save()
+        sim.step(10)
+        sim.load(state)
+        sim.sync()
+        t = time.perf_counter()
+        sim.step(steps)
+        sim.sync()
+        fwd = time.perf_counter() - t
+        sim.load(state)
+        t = time.perf_counter()
+        J, gc, gp = sim.adjoint(steps, interval)
+        adj = time.perf_counter() - t
+        grads[prec] = (J, gc, gp, sim, state)
+        out[prec] = {"J": J, "seconds": adj,
+                     "ms_per_step": adj / steps * 1e3,
+                     "forward_ms_per_step": fwd / steps * 1e3}
+        print("  adjoint %s: %.3f s for %d steps (%.3f ms/step; forward "
+              "alone %.3f ms/step), J = %.10f" % (prec, adj, steps,
+                                                  adj / steps * 1e3,
+                                                  fwd / steps * 1e3, J),
+              file=sys.stderr, flush=True)
+    J, gc, gp, sim, state = grads["fp64"]
+    gc32, gp32 = grads["fp32"][1], grads["fp32"][2]
+    out["fp32_vs_fp64"] = {
+        "rel_linf_grad_cos": float(np.abs(gc32 - gc).max() / np.abs(gc).max()),
+        "rel_linf_grad_psi": float(np.abs(gp32 - gp).max() / np.abs(gp).max())}
+    psi0 = np.asarray(wl.psi)
+    cos0 = np.asarray(wl.cos_theta_iN).reshape(gc.shape)
+    v = W.smooth_angle_field(wl.shape, 7, lo=-1.0, hi=1.0)[None]
+
+    def value(h):
+        sim.init_geometry(psi0, cos0 + h * v)
+        sim.load(state)
+        sim.step(steps)
+        return sim.objective()
+
+    h = 2e-3
+    d1 = (value(h) - value(-h)) / (2 * h)
+    d2 = (value(h / 2) - value(-h / 2)) / h
+    fd = (4.0 * d2 - d1) / 3.0
+    ad = float((gc * v).sum())
+    out["fd_check_fp64"] = {"adjoint": ad, "finite_differences": fd,
+                            "rel_err": abs(fd - ad) / abs(ad)}
+    for p in grads.values():
+        p[3].close()
+    return out
+
+
 def copy_calibration(torch, mib=1024):
     """A plain device copy of known size, for scaling the HBM byte counters
     (FETCH_SIZE / WRITE_SIZE) read on the step kernel."""
@@ -338,6 +403,10 @@ def main():
     ap.add_argument("--batch", type=int, default=256,
                     help="also time this many batched instances (0: skip)")
     ap.add_argument("--batch-steps", type=int, default=200)
+    ap.add_argument("--adjoint", type=int, default=256,
+                    help="also time the adjoint sweep on the n x n channel "
+                         "(0: skip)")
+    ap.add_argument("--adjoint-steps", type=int, default=2000)
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--traffic-summary", nargs=2, metavar=("FETCH_DIR",
                                                            "WRITE_DIR"),
@@ -404,6 +473,11 @@ def main():
         print("timing %d batched instances" % a.batch, file=sys.stderr,
               flush=True)
         batched = batched_leg(a.batch, a.batch_steps, torch)
+    adjoint = None
+    if a.adjoint:
+        print("timing the adjoint sweep on the %d^2 channel" % a.adjoint,
+              file=sys.stderr, flush=True)
+        adjoint = adjoint_leg(a.adjoint, a.adjoint_steps, 100, torch)
     err = None
     cpu = None
     if not a.skip_cpu:
@@ -413,7 +487,7 @@ def main():
         cpu = cpu_baseline(wl, a.cpu_steps)
     if "fp32" not in res:
         print(json.dumps({"fp64": res["fp64"], "sphere3d": sphere,
-                          "batched": batched}))
+                          "batched": batched, "adjoint": adjoint}))
         return 0
     f32 = res["fp32"]
     line = {
@@ -434,6 +508,7 @@ def main():
         "fp64": res.get("fp64"),
         "sphere3d": sphere,
         "batched": batched,
+        "adjoint": adjoint,
     }
     print(json.dumps(line), flush=True)
     return 0

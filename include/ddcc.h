@@ -178,6 +178,46 @@ int ddcc_load(ddcc_ctx* ctx, const void* buf, size_t bytes);
 /* Waits for all work queued on the context stream. */
 int ddcc_sync(ddcc_ctx* ctx);
 
+/* ---- Adjoint (reverse-time) sweep ------------------------------------------
+ * Gradient of a phase-weighted objective of the state after nsteps steps,
+ *   J = sum_x w(x) phi C_k(x) / sum_x phi C_k(x),   phi C_k = sum_p f^k_p,
+ * (w(x) = x, the node index along x, gives the centroid x of phase k; an
+ * indicator of a region gives the fraction of phase k inside it) with
+ * respect to the per-node wetting angles cos theta_iN (eq. 2.9) and the
+ * smooth characteristic function psi (Section 2), the state at the call
+ * (populations and history) held fixed. The derivative is that of the
+ * library's discrete step, transposed by hand stage by stage: collision
+ * (eqs. 3.1-3.4), equilibria and sources (3.5-3.12), force and velocity
+ * (3.13), pressure (eq. 19), chemical potential (2.14), mobility (2.5),
+ * the finite-difference stencils, pull streaming. |grad psi| is taken to
+ * have derivative 0 where grad psi = 0.
+ *
+ * Runs the nsteps forward steps (checkpointing the state every `interval`
+ * steps on the device), evaluates J, then sweeps back one segment of
+ * `interval` steps at a time, recomputing the segment's states from its
+ * checkpoint. Device memory: about (nsteps / interval + interval + 1)
+ * states plus a few adjoint states, released on return. On success the
+ * context is left at the final level (time advanced by nsteps).
+ *
+ * weight     host [ny][nx] float64, finite (the w above)
+ * phase      k in [0, nphase)
+ * J          host scalar out (may be NULL)
+ * grad_cos   host [nphase - 1][ny][nx] out: dJ/dcos theta_iN (may be NULL)
+ * grad_psi   host [ny][nx] out: dJ/dpsi (may be NULL)
+ * Needs a 2D FP64 or FP32 context whose geometry came from one wall
+ * (ddcc_init_geometry). Errors: DDCC_E_INVAL (bad argument), DDCC_E_STATE
+ * (before init_fields), DDCC_E_UNSUPPORTED (3D, 16-bit storage, several
+ * walls), DDCC_E_NONFINITE (zero or non-finite phase mass at the end),
+ * DDCC_E_NOMEM, DDCC_E_HIP. Synchronises. */
+int ddcc_adjoint(ddcc_ctx* ctx, int64_t nsteps, int interval, int phase,
+                 const double* weight, double* J, double* grad_cos,
+                 double* grad_psi);
+
+/* The objective J of ddcc_adjoint on the current state, without stepping:
+ * sum_x w(x) phi C_k(x) / sum_x phi C_k(x) in float64. weight: host
+ * [ny][nx]. 2D FP64 or FP32 contexts. Errors as ddcc_adjoint. Synchronises. */
+int ddcc_objective(ddcc_ctx* ctx, int phase, const double* weight, double* J);
+
 /* Kernel launch shape of the step kernel: tile (tx, ty) of nodes per
  * workgroup; 0 keeps the default. tx is 64 (one wavefront per row); ty is
  * 2, 4, 8 or 16 in 2D (default 8) and 2 or 4 in 3D (default 4). Any other

@@ -12,7 +12,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libddcc.so")
-SOURCES = ["api.cpp", "step2d.hip", "step3d.hip", "util.hip"]
+SOURCES = ["api.cpp", "adjoint_api.cpp", "step2d.hip", "step3d.hip",
+           "util.hip", "adjoint2d.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 

@@ -10,40 +10,11 @@
 
 #include "../../include/ddcc.h"
 #include "coef.hpp"
+#include "ctx.hpp"
 #include "kernels.hpp"
 #include "lattice.hpp"
 
 using namespace ddcc;
-
-struct ddcc_ctx {
-  ddcc_params p{};
-  hipStream_t stream = nullptr;
-  bool own_stream = false;
-  int device = 0;
-  long long n = 0;
-  int Qf = 0, Qg = 0, nhist = 0, nT = 0;
-  size_t esz = 8;   // history, T and geometry fields
-  size_t pesz = 8;  // moving populations
-  void* f[2] = {nullptr, nullptr};
-  double* f0[2] = {nullptr, nullptr};  // rest populations, float64
-  void* g[2] = {nullptr, nullptr};
-  void* T[2] = {nullptr, nullptr};
-  void* hist = nullptr;
-  void* psi = nullptr;
-  void* wet = nullptr;         // wetting weights [N-1][n]
-  double* work = nullptr;     // 3D: C_i and mu_i fields, 2 N n float64
-  double* staging = nullptr;  // (N + dim + 1) * n float64, lazily
-  double* partial = nullptr;
-  int* bad = nullptr;
-  int mass_blocks = 0;
-  int cur = 0;
-  bool geom_ok = false, fields_ok = false;
-  int64_t t = 0;
-  int tile_x = 64, tile_y = 8;
-  std::string err;
-  Coef<double> kd{};
-  Coef<float> kf{};
-};
 
 namespace {
 
@@ -424,7 +395,20 @@ struct SaveHeader {
 
 namespace ddcc {
 bool have_3d();
+
+namespace detail {
+int fail(ddcc_ctx* c, int code, const std::string& msg) {
+  return ::fail(c, code, msg);
 }
+int hip_fail(ddcc_ctx* c, hipError_t e, const char* what) {
+  return ::hip_fail(c, e, what);
+}
+hipError_t step_launch(ddcc_ctx* c) {
+  return launch(c, MODE_STEP, nullptr, nullptr, nullptr, nullptr, nullptr,
+                nullptr);
+}
+}  // namespace detail
+}  // namespace ddcc
 
 extern "C" {
 
@@ -521,6 +505,11 @@ int ddcc_create(const ddcc_params* p, void* stream, ddcc_ctx** out) {
     e = hipMalloc(&c->partial,
                   (size_t)c->mass_blocks * p->nphase * sizeof(double));
   if (e == hipSuccess) e = hipMalloc(&c->bad, (size_t)c->mass_blocks * sizeof(int));
+  // plane 0 of the phase buffers is never written by the kernels (the rest
+  // populations live in f0): zero it so that checkpoints are deterministic
+  for (int a = 0; a < 2 && e == hipSuccess; ++a)
+    e = hipMemsetAsync(c->f[a], 0, sf, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) {
     release(c);
     delete c;
@@ -559,6 +548,7 @@ static int geometry_from_device(ddcc_ctx* c, int K, const double* psik,
                                     c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "geometry kernel");
   c->geom_ok = true;
+  c->nwalls = K;
   c->fields_ok = false;
   return DDCC_OK;
 }

@@ -84,6 +84,9 @@ def _load():
         "ddcc_load": (ctypes.c_int, [ctx, vp, ctypes.c_size_t]),
         "ddcc_sync": (ctypes.c_int, [ctx]),
         "ddcc_set_tile": (ctypes.c_int, [ctx, ctypes.c_int, ctypes.c_int]),
+        "ddcc_adjoint": (ctypes.c_int, [ctx, ctypes.c_int64, ctypes.c_int,
+                                        ctypes.c_int, dp, dp, dp, dp]),
+        "ddcc_objective": (ctypes.c_int, [ctx, ctypes.c_int, dp, dp]),
         "ddcc_last_error": (ctypes.c_char_p, [ctx]),
         "ddcc_destroy": (None, [ctx]),
         "ddcc_version": (ctypes.c_char_p, []),
@@ -132,6 +135,8 @@ ddcc_save = LIB.ddcc_save
 ddcc_load = LIB.ddcc_load
 ddcc_sync = LIB.ddcc_sync
 ddcc_set_tile = LIB.ddcc_set_tile
+ddcc_adjoint = LIB.ddcc_adjoint
+ddcc_objective = LIB.ddcc_objective
 ddcc_last_error = LIB.ddcc_last_error
 ddcc_destroy = LIB.ddcc_destroy
 ddcc_version = LIB.ddcc_version
@@ -201,6 +206,12 @@ def make_params(dim, shape, nphase, lattice_f, lattice_g, precision="fp64",
             for a, v in enumerate(prm[key]):
                 arr[a] = float(v)
     return p
+
+
+def centroid_weight(shape):
+    """w(x) = x, the node index along x (the last array axis)."""
+    return np.ascontiguousarray(np.broadcast_to(
+        np.arange(shape[-1], dtype=np.float64), shape))
 
 
 def _dptr(a):
@@ -318,6 +329,29 @@ class Sim:
 
     def set_tile(self, tx=0, ty=0):
         self._check(LIB.ddcc_set_tile(self._h, int(tx), int(ty)))
+
+    def adjoint(self, nsteps, interval=100, phase=0, weight=None):
+        """ddcc_adjoint: J and its gradients (dJ/dcos theta_iN of shape
+        (nphase - 1,) + shape, dJ/dpsi of shape `shape`) over the next
+        nsteps steps; weight defaults to the node index along x (J is then
+        the centroid x of `phase`). The context advances by nsteps."""
+        w = centroid_weight(self.shape) if weight is None else _c64(weight)
+        J = ctypes.c_double(0.0)
+        gc = np.empty((self.nphase - 1,) + self.shape)
+        gp = np.empty(self.shape)
+        self._check(LIB.ddcc_adjoint(self._h, int(nsteps), int(interval),
+                                     int(phase), _dptr(w), ctypes.byref(J),
+                                     _dptr(gc), _dptr(gp)))
+        return J.value, gc, gp
+
+    def objective(self, phase=0, weight=None):
+        """ddcc_objective: sum w phi C_k / sum phi C_k on the current state
+        (weight defaults to the node index along x)."""
+        w = centroid_weight(self.shape) if weight is None else _c64(weight)
+        J = ctypes.c_double(0.0)
+        self._check(LIB.ddcc_objective(self._h, int(phase), _dptr(w),
+                                       ctypes.byref(J)))
+        return J.value
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

@@ -253,6 +253,71 @@ def wavy_channel_2d(n=256, theta_bottom=(120.0, 60.0), theta_top=(120.0, 60.0),
     return wl
 
 
+def _distance_to_curve(x, y, xc, yc, n):
+    """Minimum-image distance from the nodes (x, y) to the polyline of
+    samples (xc, yc) on the periodic n x n box."""
+    best = np.full(x.shape, np.inf)
+    for xs, ys in zip(xc, yc):
+        dx = _periodic_delta(x, xs, n)
+        dy = _periodic_delta(y, ys, n)
+        np.minimum(best, dx * dx + dy * dy, out=best)
+    return np.sqrt(best)
+
+
+def smooth_angle_field(shape, seed, kmax=4, lo=60.0, hi=120.0):
+    """Angles in degrees: a sum of Fourier modes with |k| <= kmax (k != 0)
+    and N(0, 1) cosine and sine coefficients, mapped affinely onto
+    [lo, hi]."""
+    rng = np.random.default_rng(seed)
+    ny, nx = shape
+    x, y = _grid(shape)
+    F = np.zeros(shape)
+    for kx in range(-kmax, kmax + 1):
+        for ky in range(-kmax, kmax + 1):
+            if (kx, ky) == (0, 0) or kx * kx + ky * ky > kmax * kmax:
+                continue
+            ph = 2.0 * math.pi * (kx * x / nx + ky * y / ny)
+            a, b = rng.standard_normal(2)
+            F += a * np.cos(ph) + b * np.sin(ph)
+    return lo + (hi - lo) * (F - F.min()) / (F.max() - F.min())
+
+
+def adjoint_channel_2d(n=256, steps=2000, seed=2312, force=1e-6):
+    """2D, N = 2, the wavy channel of the adjoint workload: bottom wall
+    y = 40 + 20 sin(2 pi x / 64) and top wall y = 216 - 20 sin(2 pi x / 64)
+    (sizes scale with n / 256), one psi from the signed distance to the
+    nearer wall (fluid between them, solid band across the periodic
+    boundary). The wetting angle theta_12 varies per node: a smooth random
+    field (Fourier modes |k| <= 4, seed 2312) mapped onto [60, 120] degrees.
+    A droplet of radius 30 rests on the bottom wall with its centre 20 cells
+    above the wall at x = n/2 (at the channel centre it would touch no wall
+    and the objective would not depend on the angles), density ratio 1, a
+    body force density `force` along x."""
+    shape = (n, n)
+    x, y = _grid(shape)
+    s = n / 256.0
+    amp, period = 20.0 * s, 64.0 * s
+    xs = np.arange(0.0, n, 0.125)
+    yb = 40.0 * s + amp * np.sin(2.0 * math.pi * xs / period)
+    yt = 216.0 * s - amp * np.sin(2.0 * math.pi * xs / period)
+    d = np.minimum(_distance_to_curve(x, y, xs, yb, n),
+                   _distance_to_curve(x, y, xs, yt, n))
+    ybx = 40.0 * s + amp * np.sin(2.0 * math.pi * x / period)
+    ytx = 216.0 * s - amp * np.sin(2.0 * math.pi * x / period)
+    inside = (y > ybx) & (y < ytx)
+    psi = psi_from_distance(np.where(inside, d, -d))
+    theta = smooth_angle_field(shape, seed)
+    ct = np.cos(np.radians(theta))[None]
+    cx = n / 2.0
+    wall = 40.0 * s + amp * math.sin(2.0 * math.pi * cx / period)
+    r = periodic_distance((x, y), (cx, wall + 20.0 * s), shape)
+    C1 = droplet(r, 30.0 * s, 5.0)
+    prm = default_params(2, 2, force=[force, 0.0])
+    return Workload("adjoint_channel_2d", 2, shape, "D2Q9", "D2Q9", prm, psi,
+                    ct, np.stack([C1, 1.0 - C1]), np.zeros((2,) + shape),
+                    np.zeros(shape), steps)
+
+
 BATCH_SIDES = (64, 96, 128, 192, 256)
 
 
