@@ -1,6 +1,7 @@
 // Host side of ddcc_adjoint (include/ddcc.h): forward sweep with periodic
 // checkpoints, objective and seed, reverse sweep segment by segment
-// (recomputing each segment's states from its checkpoint), final gradients.
+// (recomputing each segment's states from its checkpoint, the step kernel
+// writing each state straight into its slot), final gradients.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -10,6 +11,7 @@
 #include "../../include/ddcc.h"
 #include "adjoint.hpp"
 #include "ctx.hpp"
+#include "kernels.hpp"
 
 using namespace ddcc;
 using detail::fail;
@@ -88,6 +90,44 @@ AdjFwd<S> view(const char* slot, const Layout& L) {
   return v;
 }
 
+template <class R>
+const Coef<R>& coef_of(const ddcc_ctx* c);
+template <>
+const Coef<double>& coef_of<double>(const ddcc_ctx* c) {
+  return c->kd;
+}
+template <>
+const Coef<float>& coef_of<float>(const ddcc_ctx* c) {
+  return c->kf;
+}
+
+// One forward step from the state stored in slot `from` into slot `to`
+// (the history is updated in place, so it is copied over first).
+template <class S>
+hipError_t step_between(ddcc_ctx* c, const char* from, char* to,
+                        const Layout& L) {
+  const size_t oh = L.sf + L.s0 + L.sg;
+  const size_t sh = (size_t)c->nhist * (size_t)c->n * c->esz;
+  hipError_t e = hipMemcpyAsync(to + oh, from + oh, sh, hipMemcpyDeviceToDevice,
+                                c->stream);
+  if (e != hipSuccess) return e;
+  Bufs<S, S> b{};
+  const AdjFwd<S> a = view<S>(from, L);
+  b.fA = a.f;
+  b.f0A = a.f0;
+  b.gA = a.g;
+  b.TA = a.T;
+  b.fB = reinterpret_cast<S*>(to);
+  b.f0B = reinterpret_cast<double*>(to + L.sf);
+  b.gB = reinterpret_cast<S*>(to + L.sf + L.s0);
+  b.hist = reinterpret_cast<S*>(to + oh);
+  b.TB = reinterpret_cast<S*>(to + oh + L.sh);
+  b.psi = static_cast<const S*>(c->psi);
+  b.wet = static_cast<const S*>(c->wet);
+  return launch_2d<S, S, S>(c->p.nphase, MODE_STEP, c->kd, coef_of<S>(c), b,
+                            c->tile_y, c->stream);
+}
+
 int forward_step(ddcc_ctx* c) {
   hipError_t e = detail::step_launch(c);
   if (e != hipSuccess) return hip_fail(c, e, "step kernel");
@@ -138,7 +178,6 @@ int adjoint_as(ddcc_ctx* c, int64_t nsteps, int interval, int phase,
   using R = double;
   const int N = c->p.nphase;
   const size_t n = (size_t)c->n;
-  const int64_t t0 = c->t;
   const Layout L = state_layout(c);
   const int64_t nck = (nsteps + interval - 1) / interval;
   const int64_t seg = nsteps < interval ? nsteps : interval;
@@ -215,13 +254,13 @@ int adjoint_as(ddcc_ctx* c, int64_t nsteps, int interval, int phase,
   for (int64_t sg = nck - 1; sg >= 0; --sg) {
     const int64_t s0 = sg * interval;
     const int64_t s1 = s0 + interval < nsteps ? s0 + interval : nsteps;
-    ACHK(copy_state(c, ck0 + (size_t)sg * L.total, L, false), "restore checkpoint");
-    for (int64_t s = s0; s < s1; ++s) {
-      ACHK(copy_state(c, seg0 + (size_t)(s - s0) * L.total, L, true), "store state");
-      if (s < s1 - 1) {
-        rc = forward_step(c);
-        if (rc) return rc;
-      }
+    // the segment's states, each written by the step straight into its slot
+    ACHK(hipMemcpyAsync(seg0, ck0 + (size_t)sg * L.total, L.total,
+                        hipMemcpyDeviceToDevice, c->stream),
+         "restore checkpoint");
+    for (int64_t s = s0; s < s1 - 1; ++s) {
+      char* from = seg0 + (size_t)(s - s0) * L.total;
+      ACHK(step_between<S>(c, from, from + L.total, L), "step kernel");
     }
     for (int64_t s = s1 - 1; s >= s0; --s) {
       AdjBufs<R> ab;
@@ -257,9 +296,8 @@ int adjoint_as(ddcc_ctx* c, int64_t nsteps, int interval, int phase,
     ACHK(hipMemcpyAsync(gpsi_host, gpsi_out, n * sizeof(double),
                         hipMemcpyDeviceToHost, c->stream),
          "copy gradient");
-  // leave the context at the final level of the forward sweep
-  ACHK(copy_state(c, fin, L, false), "restore final state");
-  c->t = t0 + nsteps;
+  // the reverse sweep works on the stored states only: the context still
+  // holds the final level of the forward sweep
   ACHK(hipStreamSynchronize(c->stream), "sync");
   return DDCC_OK;
 }

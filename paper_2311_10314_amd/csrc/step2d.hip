@@ -170,11 +170,14 @@ struct Step2D {
   }
 
   // Phase 1 at C-region coordinates (lx, ly).
-  template <class G>
+  // Kept: the pulled moving populations (own node) are written to `keep`
+  // and handed on to phase 3 in registers instead of being loaded again.
+  using Keep = R[N][Q];
+  template <bool KEPT = false, class G>
   __device__ static inline void node1(Smem& sm, const Coef<D>& k,
                                       const Bufs<Pop, S>& b, const G& gd, int x0,
                                       int y0, int lx,
-                                      int ly, D* psiC_out) {
+                                      int ly, D* psiC_out, Keep* keep = nullptr) {
     const int gx = wrap(x0 + lx - 2, gd.nx), gy = wrap(y0 + ly - 2, gd.ny);
     const unsigned idx = gd.off + unsigned(gy * gd.nx + gx);
     const D psi = D(ldp(b.psi, idx));
@@ -193,8 +196,11 @@ struct Step2D {
         // rest population added last
         R mv = R(0);
 #pragma unroll
-        for (int p = 1; p < Q; ++p)
-          mv += R(ldp(f + (long long)(p) * gd.n, nb.src(D2Q9::c[p].x, D2Q9::c[p].y)));
+        for (int p = 1; p < Q; ++p) {
+          const R v = R(ldp(f + (long long)(p) * gd.n, nb.src(D2Q9::c[p].x, D2Q9::c[p].y)));
+          if constexpr (KEPT) (*keep)[i][p] = v;
+          mv += v;
+        }
         psiC_out[i] = ldp(b.f0A + (long long)(i) * gd.n, idx) + D(mv);
       }
     }
@@ -298,7 +304,12 @@ struct Step2D {
     const int tid = threadIdx.x;
     const int tx = tid % TX, ty = tid / TX;
     D psiC[N], psimu_d[N], dummy[N];
-    node1(sm, kd, b, kd, x0, y0, tx + 2, ty + 2, psiC);
+    // float arithmetic: the own node's pulled populations stay in registers
+    // from phase 1 to the collision (phase 3 would otherwise load them
+    // again, after the whole chunk's phase-1 traffic has gone through L2)
+    constexpr bool KEEP = MODE == MODE_STEP && sizeof(R) == 4;
+    Keep fown;
+    node1<KEEP>(sm, kd, b, kd, x0, y0, tx + 2, ty + 2, psiC, &fown);
     for (int r = tid; r < RING1; r += NT) {
       int lx, ly;
       ring1(r, lx, ly);
@@ -313,8 +324,8 @@ struct Step2D {
     }
     __syncthreads();
     if (x0 + tx < k.nx && y0 + ty < k.ny)
-      node3(sm, kd, k, b, Grid{k.nx, k.ny, k.n, 0u}, x0, y0, tx, ty, psiC,
-            psimu_d);
+      node3<KEEP>(sm, kd, k, b, Grid{k.nx, k.ny, k.n, 0u}, x0, y0, tx, ty,
+                  psiC, psimu_d, &fown);
   }
 
   // One TX x TY tile with its corner at (x0, y0) of box gd. Every thread of
@@ -327,7 +338,9 @@ struct Step2D {
     const int tid = threadIdx.x;
     const int tx = tid % TX, ty = tid / TX;
     D psiC[N], psimu_d[N], dummy[N];
-    node1(sm, kd, b, gd, x0, y0, tx + 2, ty + 2, psiC);
+    constexpr bool KEEP = MODE == MODE_STEP && sizeof(R) == 4;
+    Keep fown;
+    node1<KEEP>(sm, kd, b, gd, x0, y0, tx + 2, ty + 2, psiC, &fown);
     for (int r = tid; r < RING1; r += NT) {
       int lx, ly;
       ring1(r, lx, ly);
@@ -342,14 +355,16 @@ struct Step2D {
     }
     __syncthreads();
     if (x0 + tx < gd.nx && y0 + ty < gd.ny)
-      node3(sm, kd, k, b, gd, x0, y0, tx, ty, psiC, psimu_d);
+      node3<KEEP>(sm, kd, k, b, gd, x0, y0, tx, ty, psiC, psimu_d, &fown);
   }
 
   // Phase 3 for the own node (x0 + tx, y0 + ty) of the tile.
+  template <bool KEPT = false>
   __device__ static inline void node3(const Smem& sm, const Coef<D>& kd,
                                       const Coef<R>& k, const Bufs<Pop, S>& b,
                                       const Grid& gd, int x0, int y0, int tx,
-                                      int ty, const D* psiC, const D* psimu_d) {
+                                      int ty, const D* psiC, const D* psimu_d,
+                                      const Keep* kept = nullptr) {
     R psimu[N];
 #pragma unroll
     for (int i = 0; i < N; ++i) psimu[i] = R(psimu_d[i]);
@@ -557,7 +572,10 @@ struct Step2D {
         fp[0] = R(0);
 #pragma unroll
         for (int p = 1; p < Q; ++p)
-          fp[p] = R(ldp(fsrc + (long long)(p) * n, nb.src(D2Q9::c[p].x, D2Q9::c[p].y)));
+          if constexpr (KEPT)
+            fp[p] = (*kept)[i][p];
+          else
+            fp[p] = R(ldp(fsrc + (long long)(p) * n, nb.src(D2Q9::c[p].x, D2Q9::c[p].y)));
         R del[Q];
         collide_phase<D2Q9>(fp, em, X, V, k.sf, k.cs2, del);
         D comp = D(0);
