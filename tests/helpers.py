@@ -58,3 +58,47 @@ def gpu_state_to_oracle(wl, sim):
         T[a, b] = Tg[k]
         T[b, a] = -Tg[k]
     return State(f, g, X, Y, P, T)
+
+
+def window_state(wl, s, center, hw):
+    """Oracle State on the (2 hw + 1)^d window of nodes around `center`
+    (array indices, periodic), built from an unpack_state dict s of a
+    library checkpoint. The window's own periodic wrap is wrong only near
+    its edge: a node's next state depends on the state within 4 nodes, so
+    outputs within hw - 4 of the centre are those of the full box."""
+    from oracle.dd_cclb import State
+    from paper_2311_10314_amd.ddcc import streamed
+    N, d = s["N"], s["dim"]
+    shape = wl.shape
+    pad = [(np.arange(-hw - 1, hw + 2) + c) % n for c, n in zip(center, shape)]
+    sub = lambda a: a[(Ellipsis,) + np.ix_(*pad)]
+    crop = (Ellipsis,) + (slice(1, -1),) * d
+    f = np.stack([streamed(np.asarray(sub(s["f"][i]), np.float64), s["lf"])
+                  for i in range(N)])[crop]
+    g = streamed(np.asarray(sub(s["g"]), np.float64), s["lg"])[crop]
+    g[0] += wl.params["rho0"]
+    h = np.asarray(sub(s["hist"]), np.float64)[crop]
+    wshape = h.shape[1:]
+    X = h[:N * d].reshape((N, d) + wshape)
+    Y = np.zeros((d, d) + wshape)
+    T = np.zeros((d, d) + wshape)
+    o = N * d
+    pairs = [(a, b) for a in range(d) for b in range(a, d)]
+    for k, (a, b) in enumerate(pairs):
+        Y[a, b] = h[o + k]
+        Y[b, a] = h[o + k]
+    P = h[o + len(pairs)].copy()
+    tpairs = [(a, b) for a in range(d) for b in range(a + 1, d)]
+    Tg = np.asarray(sub(s["T"]), np.float64)[crop]
+    for k, (a, b) in enumerate(tpairs):
+        T[a, b] = Tg[k]
+        T[b, a] = -Tg[k]
+    return State(f, g, X, Y, P, T)
+
+
+def window(a, center, hw):
+    """The (2 hw + 1)^d periodic window of a grid array (last axes)."""
+    d = len(center)
+    shape = a.shape[-d:]
+    idx = [(np.arange(-hw, hw + 1) + c) % n for c, n in zip(center, shape)]
+    return a[(Ellipsis,) + np.ix_(*idx)]

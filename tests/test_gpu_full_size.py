@@ -1,0 +1,105 @@
+"""Parity at the benchmarked sizes, on sampled outputs.
+
+* 3D droplet impacting a sphere, 256^3 (the bench's 3D box and launch
+  shape): after some steps on the GPU, one more GPU step is compared at
+  sampled nodes with one oracle step taken on a periodic window of the GPU
+  state around each sample (a node's next state depends on the state
+  within 4 nodes, so the window's centre is exact). Samples: random nodes,
+  nodes on the sphere's wall layer and on the droplet interface, nodes at
+  the periodic boundary.
+* The batched workload with all 256 instances (FP32, graph step loop, the
+  autotuned tile as in the bench): the smallest instances against full
+  oracle runs of the same steps.
+"""
+import functools
+
+import numpy as np
+import pytest
+
+from paper_2311_10314_amd import workloads as W
+from tests.helpers import oracle_run, rel_linf, window, window_state
+
+pytestmark = pytest.mark.gpu
+
+HW = 5
+
+
+@functools.lru_cache(maxsize=1)
+def _sphere256():
+    return W.droplet_impact_sphere_3d(n=256)
+
+
+def _samples(wl, rng, count=24):
+    shape = wl.shape
+    out = [tuple(int(rng.integers(0, n)) for n in shape) for _ in range(count)]
+    psi = np.asarray(wl.psi)
+    C = np.asarray(wl.C0[0])
+    for mask in ((psi > 0.2) & (psi < 0.8), (C > 0.2) & (C < 0.8) & (psi > 0.9)):
+        idx = np.argwhere(mask)
+        pick = rng.choice(len(idx), size=min(8, len(idx)), replace=False)
+        out += [tuple(int(v) for v in idx[k]) for k in pick]
+    out += [(0, 0, 0), (shape[0] - 1, shape[1] // 2, shape[2] - 1)]
+    return out
+
+
+# FP16: one step of 16-bit storage rounds each moving population by up to
+# u_s |f| (u_s = 2^-11); relative to the largest population 3e-3 is 6 u_s.
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 1e-5),
+                                           ("fp16", 3e-3)])
+def test_sphere_full_size_sampled_one_step(precision, tol):
+    import oracle
+    from paper_2311_10314_amd.ddcc import Sim, unpack_state
+    wl = _sphere256()
+    print("sphere 256^3 %s" % precision, flush=True)
+    sim = Sim.from_workload(wl, precision)
+    sim.step(20)
+    s0 = unpack_state(sim, sim.save())
+    sim.step(1)
+    s1 = unpack_state(sim, sim.save())
+    sim.close()
+    prm, _, _ = oracle.from_workload(wl)
+    rng = np.random.default_rng(256)
+    worst = 0.0
+    c = (HW,) * 3
+    for center in _samples(wl, rng):
+        geo = oracle.Geometry(prm, window(np.asarray(wl.psi), center, HW),
+                              window(np.asarray(wl.cos_theta_iN), center, HW))
+        st1 = oracle.step(prm, geo, window_state(wl, s0, center, HW))
+        got = window_state(wl, s1, center, HW)
+        for a, b in ((got.f, st1.f), (got.g, st1.g)):
+            ref = b[(Ellipsis,) + c]
+            err = np.abs(a[(Ellipsis,) + c] - ref).max() / np.abs(ref).max()
+            worst = max(worst, err)
+            if not err < tol:
+                print("node", center, "error %.2e" % err, flush=True)
+    print("sphere 256^3 %s: worst relative population error over %d nodes "
+          "%.2e" % (precision, len(_samples(wl, np.random.default_rng(256))),
+                    worst), flush=True)
+    assert worst < tol
+
+
+def test_batched_full_workload_small_instances():
+    from paper_2311_10314_amd.ddcc import Batch
+    wls = W.batched_instances(256)
+    steps = 20
+    b = Batch.from_workloads(wls, "fp32")
+    ty = b.autotune(3)
+    b.set_graph(10)
+    m0 = {}
+    order = sorted(range(len(wls)), key=lambda i: wls[i].nodes)[:3]
+    for i in order:
+        m0[i] = b.mass(i)
+    t0 = b.time
+    b.step(steps)
+    assert b.time == t0 + steps
+    for i in order:
+        wl = wls[i]
+        o = oracle_run(wl, t0 + steps)
+        C, u = b.read_moments(i)[:2]
+        eC = max(rel_linf(C[k], o["C"][k]) for k in range(len(o["C"])))
+        eu = rel_linf(u, o["u"])
+        drift = float(np.max(np.abs(b.mass(i) - m0[i]) / np.abs(m0[i])))
+        print("instance %d %s (tile rows %d): C %.2e u %.2e drift %.1e" % (
+            i, wl.shape, ty, eC, eu, drift), flush=True)
+        assert eC < 1e-5 and eu < 1e-5 and drift < 1e-6
+    b.close()
