@@ -126,16 +126,27 @@ __device__ inline Star<T> gather(const S* plane, const Nbr3& nb) {
   return s;
 }
 
-// Node of this thread; false outside the grid. Natural tile order: the
-// 8 XCDs take workgroups round-robin, so consecutive tiles of a plane spread
-// over all XCDs and the chip sweeps the box plane by plane (measured faster
-// than giving each XCD its own slab of planes).
+// Node of this thread; false outside the grid. The chip sweeps the box
+// plane by plane (workgroups are dispatched z-major; giving each XCD its own
+// slab of planes was slower). Within a plane, workgroup w runs on XCD w % 8,
+// and each XCD takes one contiguous band of tile rows (when the plane's tile
+// count is a multiple of 8), so the rows shared by neighbouring tiles of a
+// plane, and of the planes above and below, stay in one L2 (1.4-2.4 %
+// faster at 256^3, measured).
 template <int TY>
 __device__ inline bool node_of(const int nx, const int ny, int& x, int& y,
                                int& z) {
   z = int(blockIdx.z);
-  y = int(blockIdx.y) * TY + int(threadIdx.x) / TX;
-  x = int(blockIdx.x) * TX + int(threadIdx.x) % TX;
+  const unsigned gx = gridDim.x, per = gx * gridDim.y;
+  unsigned bx = blockIdx.x, by = blockIdx.y;
+  if (per % 8u == 0u) {
+    const unsigned l = by * gx + bx, q = per / 8u;
+    const unsigned t = (l % 8u) * q + l / 8u;
+    bx = t % gx;
+    by = t / gx;
+  }
+  y = int(by) * TY + int(threadIdx.x) / TX;
+  x = int(bx) * TX + int(threadIdx.x) % TX;
   return x < nx && y < ny;
 }
 
