@@ -86,6 +86,22 @@ def test_create_rejects_bad_arrays():
     assert ddcc.ddcc_create(ctypes.byref(p), None, ctypes.byref(h)) == 1
 
 
+def test_create_rejects_degenerate_and_oversized_grids():
+    from paper_2311_10314_amd import ddcc
+    h = ctypes.c_void_p()
+    p = _params(nx=0)
+    assert ddcc.ddcc_create(ctypes.byref(p), None, ctypes.byref(h)) == 1
+    p = _params(nx=1 << 15, ny=(1 << 14) + 1)      # 2^29 + 2^15 nodes
+    assert ddcc.ddcc_create(ctypes.byref(p), None, ctypes.byref(h)) == 1
+    p = _params(nz=2)                               # 2D with nz != 1
+    assert ddcc.ddcc_create(ctypes.byref(p), None, ctypes.byref(h)) == 1
+    p = _params(nphase=1)
+    assert ddcc.ddcc_create(ctypes.byref(p), None, ctypes.byref(h)) == 1
+    p = _params(nphase=5)
+    assert ddcc.ddcc_create(ctypes.byref(p), None, ctypes.byref(h)) == 1
+    assert not h.value
+
+
 def test_null_context_calls_fail_cleanly():
     from paper_2311_10314_amd import ddcc
     assert ddcc.ddcc_step(None, 1) == ddcc.DDCC_E_INVAL
