@@ -6,7 +6,9 @@
 //             C_i = phi C_i / sum_j phi C_j, written as a float64 field;
 //   k_mu3d    phi mu_i (eq. 2.14) from C_j and psi on the 18 D3Q19
 //             neighbours (div(psi grad C_j)) and the static wetting weights,
-//             mu_i = phi mu_i / psi_hat written as a float64 field;
+//             mu_i = phi mu_i / psi_hat written as a float64 field (each
+//             workgroup marches a column of tiles in z with three planes of
+//             C_j and psi in LDS);
 //   k_step3d  gradients of C_i, mu_i, psi and psi rho and the divergence of
 //             the lagged flux tensor T from the neighbours, mobility terms
 //             (eqs. 2.5, 3.7), force and implicit-penalty velocity (eq.
@@ -189,53 +191,118 @@ __global__ __launch_bounds__(TX* TY) void k_frac3d(Coef<double> k,
 }
 
 // ---- k_mu3d ---------------------------------------------------------------
+// z-marching: a workgroup owns a TX x TY column of nodes over ZB planes and
+// keeps three planes of C_j and psi (tile plus a one-node halo) in an LDS
+// ring, so each value is fetched once per tile instead of once per
+// neighbour (the 19-point stencil otherwise issues 19 loads per node and
+// field through L2). Loads, sums and their order are those of the gathered
+// form.
+constexpr int ZB = 16;  // planes per workgroup
+
 template <int N, class Pop, class S, int TY>
 __global__ __launch_bounds__(TX* TY) void k_mu3d(Coef<double> k, Bufs<Pop, S> b) {
   using D = double;
-  int x, y, z;
-  if (!node_of<TY>(k.nx, k.ny, x, y, z)) return;
-  const Nbr3 nb = make_nbr3(x, y, z, k.nx, k.ny, k.nz);
-  const unsigned idx = nb.at(0, 0, 0);
-  const Star<D> ps = gather<D>(b.psi, nb);
-  const D psi = ps.v[0];
-  const D psih = psi > k.psi_min ? psi : k.psi_min;
-  D C[N], L[N];
-#pragma unroll
-  for (int j = 0; j < N; ++j) {
-    const Star<D> cs = gather<D>(b.fC + (long long)j * k.n, nb);
-    C[j] = cs.v[0];
-    L[j] = sdiv_psi_grad(ps, cs);
+  constexpr int HX = TX + 2, HY = TY + 2, HN = HX * HY;
+  struct Plane {
+    D c[N][HY][HX];
+    D p[HY][HX];
+  };
+  __shared__ Plane ring[3];
+  const int nx = k.nx, ny = k.ny, nz = k.nz;
+  // tile of this workgroup (per-plane XCD banding as in node_of)
+  const unsigned gx = gridDim.x, per = gx * gridDim.y;
+  unsigned bx = blockIdx.x, by = blockIdx.y;
+  if (per % 8u == 0u) {
+    const unsigned l = by * gx + bx, q = per / 8u;
+    const unsigned t = (l % 8u) * q + l / 8u;
+    bx = t % gx;
+    by = t / gx;
   }
-  // wetting weights sum_k cos theta^k_jq |grad psi_k| from the stored
-  // E_i = sum_k cos theta^k_iN |grad psi_k| (eq. 2.9 is linear in them)
-  D ct[N];
+  const int x0 = int(bx) * TX, y0 = int(by) * TY;
+  const int z0 = int(blockIdx.z) * ZB;
+  const int z1 = z0 + ZB < nz ? z0 + ZB : nz;
+  const int tx = int(threadIdx.x) % TX, ty = int(threadIdx.x) / TX;
+  const int x = x0 + tx, y = y0 + ty;
+  const bool own = x < nx && y < ny;
+
+  auto load = [&](int zz, Plane& pl) {
+    const int zw = wrap(zz, nz);
+    for (int r = int(threadIdx.x); r < HN; r += TX * TY) {
+      const int ly = r / HX, lx = r - ly * HX;
+      const unsigned idx = (unsigned(zw) * unsigned(ny) +
+                            unsigned(wrap(y0 + ly - 1, ny))) * unsigned(nx) +
+                           unsigned(wrap(x0 + lx - 1, nx));
+      pl.p[ly][lx] = D(ldp(b.psi, idx));
 #pragma unroll
-  for (int i = 0; i < N - 1; ++i) ct[i] = D(ldp(b.wet + (long long)i * k.n, idx));
-  ct[N - 1] = D(0);
-  D W[N];  // sum_{q != j} (sum_k cos theta^k_jq |grad psi_k|) C_j C_q
+      for (int j = 0; j < N; ++j) pl.c[j][ly][lx] = ldp(b.fC + (long long)j * k.n, idx);
+    }
+  };
+
+  load(z0 - 1, ring[(z0 + 2) % 3]);
+  load(z0, ring[z0 % 3]);
+  for (int z = z0; z < z1; ++z) {
+    load(z + 1, ring[(z + 1) % 3]);
+    __syncthreads();
+    if (own) {
+      const Plane* pz[3] = {&ring[(z + 2) % 3], &ring[z % 3], &ring[(z + 1) % 3]};
+      const int lx = tx + 1, ly = ty + 1;
+      // value of a staged field at the neighbour x + c_q
+      auto at = [&](auto qc, const auto& arr) {
+        constexpr int q = decltype(qc)::value;
+        return arr(*pz[G19::c[q].z + 1], ly + G19::c[q].y, lx + G19::c[q].x);
+      };
+      const D psi = pz[1]->p[ly][lx];
+      const D psih = psi > k.psi_min ? psi : k.psi_min;
+      D C[N], L[N];
 #pragma unroll
-  for (int j = 0; j < N; ++j) {
-    D acc = D(0);
-#pragma unroll
-    for (int q = 0; q < N; ++q)
-      if (q != j) {
-        const D cjq = (k.sigN[j] * ct[j] - k.sigN[q] * ct[q]) * k.inv_sig[j][q];
-        acc += cjq * C[j] * C[q];
+      for (int j = 0; j < N; ++j) {
+        const D c0 = pz[1]->c[j][ly][lx];
+        C[j] = c0;
+        D r = D(0);
+        static_for<1, 19>([&](auto qc) {
+          constexpr int q = decltype(qc)::value;
+          const D pq = at(qc, [](const Plane& pl, int yy, int xx) { return pl.p[yy][xx]; });
+          const D cq = at(qc, [j](const Plane& pl, int yy, int xx) { return pl.c[j][yy][xx]; });
+          r += D(stencil_w<q>()) * (pq + psi) * (cq - c0);
+        });
+        L[j] = r;
       }
-    W[j] = acc;
-  }
+      const unsigned idx = (unsigned(z) * unsigned(ny) + unsigned(y)) * unsigned(nx) +
+                           unsigned(x);
+      // wetting weights sum_k cos theta^k_jq |grad psi_k| from the stored
+      // E_i = sum_k cos theta^k_iN |grad psi_k| (eq. 2.9 is linear in them)
+      D ct[N];
 #pragma unroll
-  for (int i = 0; i < N; ++i) {
-    D bulk = D(0), grad = D(0), wet = D(0);
-    const D gi = gprime(C[i]);
+      for (int i = 0; i < N - 1; ++i) ct[i] = D(ldp(b.wet + (long long)i * k.n, idx));
+      ct[N - 1] = D(0);
+      D W[N];  // sum_{q != j} (sum_k cos theta^k_jq |grad psi_k|) C_j C_q
 #pragma unroll
-    for (int j = 0; j < N; ++j)
-      if (j != i) {
-        bulk += k.beta2[i][j] * (gi - gprime(C[i] + C[j]));
-        grad += k.grad34[i][j] * L[j];
-        wet += k.wet3[i][j] * W[j];
+      for (int j = 0; j < N; ++j) {
+        D acc = D(0);
+#pragma unroll
+        for (int q = 0; q < N; ++q)
+          if (q != j) {
+            const D cjq = (k.sigN[j] * ct[j] - k.sigN[q] * ct[q]) * k.inv_sig[j][q];
+            acc += cjq * C[j] * C[q];
+          }
+        W[j] = acc;
       }
-    stp(b.fmu + (long long)i * k.n, idx, (psi * bulk + grad + wet) / psih);
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        D bulk = D(0), grad = D(0), wet = D(0);
+        const D gi = gprime(C[i]);
+#pragma unroll
+        for (int j = 0; j < N; ++j)
+          if (j != i) {
+            bulk += k.beta2[i][j] * (gi - gprime(C[i] + C[j]));
+            grad += k.grad34[i][j] * L[j];
+            wet += k.wet3[i][j] * W[j];
+          }
+        stp(b.fmu + (long long)i * k.n, idx, (psi * bulk + grad + wet) / psih);
+      }
+    }
+    // the slot of plane z - 1 is overwritten by the next iteration's load
+    __syncthreads();
   }
 }
 
@@ -524,7 +591,8 @@ hipError_t launch_3(const Coef<double>& kd, const Coef<R>& k,
   hipLaunchKernelGGL((k_frac3d<N, LF, Pop, S, R, MODE, TY>), g, blk, 0, st, kd, b);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_mu3d<N, Pop, S, TY>), g, blk, 0, st, kd, b);
+  const dim3 gm(g.x, g.y, (k.nz + ZB - 1) / ZB);
+  hipLaunchKernelGGL((k_mu3d<N, Pop, S, TY>), gm, blk, 0, st, kd, b);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_step3d<N, LF, D3Q19, Pop, S, R, MODE, TY>), g, blk, 0, st,
