@@ -307,25 +307,47 @@ __global__ __launch_bounds__(TX* TY) void k_mu3d(Coef<double> k, Bufs<Pop, S> b)
 }
 
 // ---- k_step3d -------------------------------------------------------------
+// Each workgroup marches a column of tiles in z as k_mu3d does, with three
+// planes of C_i, mu_i and psi (tile plus a one-node halo) staged in LDS; the
+// node's stencils of these fields read LDS, the rest of its inputs come from
+// global memory (256^3 step: FP32 3.17 -> 2.99 ms, FP64 5.52 -> 5.05 ms;
+// the 16-bit storages 2-6 % slower than with the gathers from L2).
+template <int N, int TY>
+struct StepPlane {
+  double c[N][TY + 2][TX + 2];
+  double m[N][TY + 2][TX + 2];
+  double p[TY + 2][TX + 2];
+};
+
+// Star of a staged field around LDS position (lx, ly) of the middle plane.
+template <class Pl, class F>
+__device__ inline Star<double> lds_star(const Pl* const* pz, int lx, int ly,
+                                        F get) {
+  Star<double> s;
+  static_for<0, 19>([&](auto qc) {
+    constexpr int q = decltype(qc)::value;
+    s.v[q] = get(*pz[G19::c[q].z + 1], ly + G19::c[q].y, lx + G19::c[q].x);
+  });
+  return s;
+}
+
 template <int N, class LF, class LG, class Pop, class S, class R, int MODE,
           int TY>
-// float64 arithmetic: at the compiler's own choice the kernel takes 256+
-// registers and runs one wave per SIMD; capped at two waves per SIMD it is
-// 6 % faster (256^3, measured), while the float32 kernels are faster
-// uncapped.
-__global__ __launch_bounds__(TX* TY)
-__attribute__((amdgpu_waves_per_eu(sizeof(R) == 8 ? 2 : 1))) void k_step3d(
-    Coef<double> kd, Coef<R> k, Bufs<Pop, S> b) {
+__device__ inline void step3d_node(const Coef<double>& kd, const Coef<R>& k,
+                                   const Bufs<Pop, S>& b, int x, int y, int z,
+                                   const StepPlane<N, TY>* const* pz, int lx,
+                                   int ly) {
   using D = double;
+  using Pl = StepPlane<N, TY>;
   constexpr int QF = LF::Q, QG = LG::Q;
-  int x, y, z;
-  if (!node_of<TY>(k.nx, k.ny, x, y, z)) return;
   const Nbr3 nb = make_nbr3(x, y, z, k.nx, k.ny, k.nz);
   const unsigned idx = nb.at(0, 0, 0);
   const long long n = k.n;
 
   // ---- gradients from the neighbours ----------------------------------
-  const Star<D> ps = gather<D>(b.psi, nb);
+  const Star<D> ps = lds_star(pz, lx, ly, [](const Pl& pl, int yy, int xx) {
+    return pl.p[yy][xx];
+  });
   const D psi_d = ps.v[0];
   const R psi = R(psi_d);
   const D psih_d = psi_d > kd.psi_min ? psi_d : kd.psi_min;
@@ -337,14 +359,18 @@ __attribute__((amdgpu_waves_per_eu(sizeof(R) == 8 ? 2 : 1))) void k_step3d(
   D mu_d[N];
 #pragma unroll
   for (int i = 0; i < N; ++i) {
-    const Star<D> cs = gather<D>(b.fC + (long long)i * n, nb);
+    const Star<D> cs = lds_star(pz, lx, ly, [i](const Pl& pl, int yy, int xx) {
+      return pl.c[i][yy][xx];
+    });
 #pragma unroll
     for (int q = 0; q < 19; ++q) rs.v[q] += kd.rho[i] * cs.v[q];
     C[i] = R(cs.v[0]);
     gC[i][0] = R(sgrad<0>(cs));
     gC[i][1] = R(sgrad<1>(cs));
     gC[i][2] = R(sgrad<2>(cs));
-    const Star<D> ms = gather<D>(b.fmu + (long long)i * n, nb);
+    const Star<D> ms = lds_star(pz, lx, ly, [i](const Pl& pl, int yy, int xx) {
+      return pl.m[i][yy][xx];
+    });
     mu_d[i] = ms.v[0];
     mu[i] = R(ms.v[0]);
     gmu[i][0] = R(sgrad<0>(ms));
@@ -583,6 +609,65 @@ __attribute__((amdgpu_waves_per_eu(sizeof(R) == 8 ? 2 : 1))) void k_step3d(
   for (int c = 0; c < 3; ++c) stp(b.TB + (long long)c * n, idx, S(Tn[c]));
 }
 
+// Waves per SIMD: float64 arithmetic is capped at two (left to itself the
+// compiler gives it 256+ registers and one wave per SIMD), float arithmetic
+// at three (172 -> 168 registers with a 24-byte spill, the occupancy its LDS
+// allows; uncapped at two waves it was 17 % slower in FP32).
+template <int N, class LF, class LG, class Pop, class S, class R, int MODE,
+          int TY>
+__global__ __launch_bounds__(TX* TY)
+__attribute__((amdgpu_waves_per_eu(sizeof(R) == 8 ? 2 : 3)))
+void k_step3d(Coef<double> kd, Coef<R> k, Bufs<Pop, S> b) {
+  using Pl = StepPlane<N, TY>;
+  constexpr int HX = TX + 2, HY = TY + 2, HN = HX * HY;
+  __shared__ Pl ring[3];
+  const int nx = k.nx, ny = k.ny, nz = k.nz;
+  const unsigned gx = gridDim.x, per = gx * gridDim.y;
+  unsigned bx = blockIdx.x, by = blockIdx.y;
+  if (per % 8u == 0u) {
+    const unsigned l = by * gx + bx, q = per / 8u;
+    const unsigned t = (l % 8u) * q + l / 8u;
+    bx = t % gx;
+    by = t / gx;
+  }
+  const int x0 = int(bx) * TX, y0 = int(by) * TY;
+  const int z0 = int(blockIdx.z) * ZB;
+  const int z1 = z0 + ZB < nz ? z0 + ZB : nz;
+  const int tx = int(threadIdx.x) % TX, ty = int(threadIdx.x) / TX;
+  const int x = x0 + tx, y = y0 + ty;
+  const bool own = x < nx && y < ny;
+
+  auto load = [&](int zz, Pl& pl) {
+    const int zw = wrap(zz, nz);
+    for (int r = int(threadIdx.x); r < HN; r += TX * TY) {
+      const int ly = r / HX, lx = r - ly * HX;
+      const unsigned i0 = (unsigned(zw) * unsigned(ny) +
+                           unsigned(wrap(y0 + ly - 1, ny))) * unsigned(nx) +
+                          unsigned(wrap(x0 + lx - 1, nx));
+      pl.p[ly][lx] = double(ldp(b.psi, i0));
+#pragma unroll
+      for (int j = 0; j < N; ++j) {
+        pl.c[j][ly][lx] = ldp(b.fC + (long long)j * k.n, i0);
+        pl.m[j][ly][lx] = ldp(b.fmu + (long long)j * k.n, i0);
+      }
+    }
+  };
+
+  load(z0 - 1, ring[(z0 + 2) % 3]);
+  load(z0, ring[z0 % 3]);
+  for (int z = z0; z < z1; ++z) {
+    load(z + 1, ring[(z + 1) % 3]);
+    __syncthreads();
+    if (own) {
+      const Pl* pz[3] = {&ring[(z + 2) % 3], &ring[z % 3], &ring[(z + 1) % 3]};
+      step3d_node<N, LF, LG, Pop, S, R, MODE, TY>(kd, k, b, x, y, z, pz,
+                                                 tx + 1, ty + 1);
+    }
+    // the slot of plane z - 1 is overwritten by the next iteration's load
+    __syncthreads();
+  }
+}
+
 template <int N, class LF, class Pop, class S, class R, int MODE, int TY>
 hipError_t launch_3(const Coef<double>& kd, const Coef<R>& k,
                     const Bufs<Pop, S>& b, hipStream_t st) {
@@ -595,8 +680,8 @@ hipError_t launch_3(const Coef<double>& kd, const Coef<R>& k,
   hipLaunchKernelGGL((k_mu3d<N, Pop, S, TY>), gm, blk, 0, st, kd, b);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_step3d<N, LF, D3Q19, Pop, S, R, MODE, TY>), g, blk, 0, st,
-                     kd, k, b);
+  hipLaunchKernelGGL((k_step3d<N, LF, D3Q19, Pop, S, R, MODE, TY>), gm, blk, 0,
+                     st, kd, k, b);
   return hipGetLastError();
 }
 
