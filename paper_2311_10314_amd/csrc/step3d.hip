@@ -1,7 +1,6 @@
 // 3D DD-CCLB step for gfx950: D3Q15 or D3Q7 phase sets, D3Q19 flow set.
 //
-// A step is three kernels on one stream, each one node per thread with no
-// workgroup barriers, so that occupancy is set by registers alone:
+// A step is three kernels on one stream:
 //   k_frac3d  pull the phase populations and sum them: phi C_i, then
 //             C_i = phi C_i / sum_j phi C_j, written as a float64 field;
 //   k_mu3d    phi mu_i (eq. 2.14) from C_j and psi on the 18 D3Q19
@@ -16,11 +15,12 @@
 //             collision (eqs. 3.1-3.12) of all sets in registers, and the
 //             post-collision populations written at the node (pull
 //             streaming).
-// Neighbour reads go through the L1/L2 caches; the chip sweeps the box plane
-// by plane, so the neighbour planes of a tile are recent. The C and mu
-// fields cost
-// 4 N float64 values of traffic per node beyond the fused minimum; in return
-// no halo is recomputed and every kernel stays at register-limited occupancy.
+// k_frac3d runs one node per thread. k_mu3d and k_step3d give each
+// workgroup a 64 x TY column of nodes over ZB planes and march it in z with
+// three planes of their stencil fields (C_j, psi; and mu_i for the step) in
+// an LDS ring, so each value is fetched once per tile instead of once per
+// neighbour. The C and mu fields cost 4 N float64 values of traffic per node
+// beyond the fused minimum; in return no halo is recomputed.
 //
 // Storage as in 2D: float64 rest populations of the phase sets in their own
 // plane, g_0 stored as g_0 - rho0, history phi C_i u (3N), Y (6), P in place,
