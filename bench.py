@@ -249,6 +249,81 @@ def copy_calibration(torch, mib=1024):
           flush=True)
 
 
+def copy_rate(torch, nbytes, reps=None):
+    """Streaming reference measured in the same session: GB/s of the
+    runtime's device-to-device copy moving `nbytes` per copy (nbytes / 2
+    read, nbytes / 2 written), alternating between two buffers so that
+    nothing is re-read from a warm cache that a step would not also have."""
+    half = max(1, int(nbytes) // 2 // 4)
+    a = torch.empty(half, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    a.zero_()
+    b.zero_()
+    if reps is None:
+        reps = max(10, min(400, int(20e9 // max(nbytes, 1))))
+    for i in range(4):
+        (b if i % 2 == 0 else a).copy_(a if i % 2 == 0 else b)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for i in range(reps):
+        (b if i % 2 == 0 else a).copy_(a if i % 2 == 0 else b)
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * half * 4 / (ms * 1e-3) / 1e9
+
+
+def sweep(torch, out_path=None):
+    """Roofline sweep of the 2D step over grid sizes, phase counts and
+    precisions: porous_bands_2d (N = 3) at 512^2 to 4096^2 and
+    disk_on_droplet_2d (N = 2) at 512^2 to 8192^2, FP32 and FP64. Each point:
+    ms per step (HIP events over enough steps to move about 20 GB),
+    node-MLUPS, algorithmic GB/s and its fraction of the 8 TB/s peak, and the
+    same-session copy rate for the same number of bytes."""
+    from paper_2311_10314_amd import workloads as W
+    points = [("porous_bands_2d", n) for n in (512, 2048, 4096)] + \
+             [("disk_on_droplet_2d", n) for n in (512, 2048, 4096, 8192)]
+    rows = []
+    for name, n in points:
+        t = time.perf_counter()
+        wl = getattr(W, name)(n=n)
+        print("sweep: %s %d^2 N=%d generated in %.1f s" % (
+            name, n, wl.nphase, time.perf_counter() - t), file=sys.stderr,
+            flush=True)
+        for prec in ("fp32", "fp64"):
+            bpn = algorithmic_bytes_per_node(wl.nphase, 2, 9, 9, prec)
+            per = bpn * wl.nodes
+            steps = max(10, min(20000, int(20e9 // per)))
+            sim, ms, drift = time_gpu(wl, prec, steps, 5, torch)
+            sim.close()
+            gbs = per / (ms * 1e-3) / 1e9
+            cp = copy_rate(torch, per)
+            r = {"workload": name, "n": n, "phases": wl.nphase,
+                 "precision": prec, "steps": steps, "ms_per_step": ms,
+                 "mlups": wl.nodes / (ms * 1e-3) / 1e6,
+                 "bytes_per_node": bpn, "algorithmic_GBs": gbs,
+                 "frac_of_peak": gbs / HBM_PEAK_GBS, "copy_GBs": cp,
+                 "frac_of_copy": gbs / cp, "mass_drift": drift}
+            rows.append(r)
+            print("  %-18s %5d^2 N=%d %s: %8.4f ms/step %7.0f MLUPS %6.0f "
+                  "GB/s (%.0f %% of peak; copy of the same bytes %.0f GB/s, "
+                  "%.0f %%)" % (name, n, wl.nphase, prec, ms, r["mlups"], gbs,
+                                100 * r["frac_of_peak"], cp,
+                                100 * r["frac_of_copy"]), file=sys.stderr,
+                  flush=True)
+        del wl
+    if out_path:
+        with open(out_path, "w") as fh:
+            json.dump(rows, fh, indent=1)
+            fh.write("\n")
+    print(json.dumps({"sweep": rows}))
+    return rows
+
+
 STEP_KERNEL = {"fp32": "float, float, float", "fp64": "double, double, double"}
 
 
@@ -408,6 +483,10 @@ def main():
                          "(0: skip)")
     ap.add_argument("--adjoint-steps", type=int, default=2000)
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--sweep", metavar="OUT_JSON", nargs="?", const="",
+                    default=None,
+                    help="run only the 2D roofline sweep over grid sizes, "
+                         "phase counts and precisions")
     ap.add_argument("--traffic-summary", nargs=2, metavar=("FETCH_DIR",
                                                            "WRITE_DIR"),
                     help="write profiles/hbm_traffic.json from two "
@@ -428,6 +507,9 @@ def main():
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
         return 1
+    if a.sweep is not None:
+        sweep(torch, a.sweep or None)
+        return 0
     wl = make_workload(a.n)
     N = wl.nphase
     res = {}
@@ -447,6 +529,7 @@ def main():
         per_launch = bpn * wl.nodes
         achieved = per_launch / (ms * 1e-3) / 1e9
         traffic = measured_traffic(prec)
+        copy = copy_rate(torch, per_launch)
         res[prec] = {
             "value": wl.nodes / (ms * 1e-3) / 1e6,
             "set_mlups": (N + 1) * wl.nodes / (ms * 1e-3) / 1e6,
@@ -456,12 +539,14 @@ def main():
                          "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": achieved / HBM_PEAK_GBS,
                          "traffic": traffic,
+                         "copy_GBs": copy,
+                         "frac_of_copy": achieved / copy,
                          "algorithmic_bytes_per_launch": per_launch,
                          "bytes_per_node": bpn},
         }
-        print("  %s: %.4f ms/step, %.0f MLUPS, %.0f GB/s" % (
-            prec, ms, res[prec]["value"], achieved), file=sys.stderr,
-            flush=True)
+        print("  %s: %.4f ms/step, %.0f MLUPS, %.0f GB/s (copy of the same "
+              "bytes: %.0f GB/s)" % (prec, ms, res[prec]["value"], achieved,
+                                    copy), file=sys.stderr, flush=True)
     sphere = None
     if a.sphere:
         print("timing the 3D sphere box at %d^3" % a.sphere, file=sys.stderr,
