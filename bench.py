@@ -499,9 +499,10 @@ def main():
                         "fp64" if a.precision == "fp64" else "fp32", a.n)
         return 0
     if a.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU "
-              "path (see the design notes for how the grid would shard)",
-              file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU "
+              "path (a grid would be cut into slabs along its slowest axis, "
+              "one per GPU, exchanging the crossing populations and a "
+              "2-cell C halo every step)", file=sys.stderr)
         return 2
     import torch
     if not torch.cuda.is_available():

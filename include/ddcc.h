@@ -46,7 +46,7 @@ extern "C" {
 #define DDCC_E_NOMEM 3       /* device allocation failed                       */
 #define DDCC_E_HIP 4         /* HIP runtime error; text in ddcc_last_error     */
 #define DDCC_E_NONFINITE 5   /* a diagnostic found NaN/Inf in the populations */
-#define DDCC_E_UNSUPPORTED 6 /* valid input this build has no kernel for      */
+#define DDCC_E_UNSUPPORTED 6 /* valid input the library has no kernel for    */
 
 /* Velocity sets (Section 3 tables; D3Q19 weights from the same moment
  * constraints). */

@@ -5,8 +5,12 @@ cpu_baseline leg of bench.py are the only users. The product path (the HIP
 library in paper_2311_10314_amd/ and its binding) never imports, links or
 runs anything here, and this package imports nothing from it.
 
-Parity status per function is listed in the design notes; every function
-here is pinned by a -m "not gpu" test in tests/test_oracle_*.py.
+Every function here is pinned by a -m "not gpu" test in
+tests/test_oracle_*.py against what the paper and the mathematics fix
+(isotropy of the weights, the BGK special case, Appendix C's pressure
+constants, mass conservation, reduction consistency, the tanh profile,
+Laplace's law, Young's angle, shear-wave, Taylor-Green and layered-channel
+solutions); oracle.adjoint against Richardson central differences.
 """
 from . import lattices, dd_cclb  # noqa: F401
 from .dd_cclb import (Params, Geometry, State, init_state, step, run,  # noqa: F401

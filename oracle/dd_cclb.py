@@ -18,8 +18,8 @@ numpy float64, each stage a whole-grid sweep in the order the scheme needs:
   collision Lambda = H^-1 S H                     eqs. (3.1)-(3.4)
   streaming (pull, periodic)                      eqs. (3.1), (3.2) left sides
 
-Readings where the paper is silent or garbled are the same as the library's
-and are listed in the design notes; each is marked "Reading:" below.
+Readings where the paper is silent or garbled are the same as the library's;
+each is marked "Reading:" below where it is applied.
 Notation: psi is the paper's smooth characteristic function phi (fluid 1,
 solid 0); phi C_i is written psiC; lattice units dx = dt = c = 1, c_s^2 = d0.
 

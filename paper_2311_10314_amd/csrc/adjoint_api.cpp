@@ -56,7 +56,8 @@ Layout state_layout(const ddcc_ctx* c) {
   return L;
 }
 
-hipError_t copy_state(ddcc_ctx* c, char* slot, const Layout& L, bool save) {
+// Copy the context's current state (populations, history, T) into a slot.
+hipError_t save_state(ddcc_ctx* c, char* slot, const Layout& L) {
   const size_t n = (size_t)c->n;
   struct Part {
     void* dev;
@@ -69,11 +70,8 @@ hipError_t copy_state(ddcc_ctx* c, char* slot, const Layout& L, bool save) {
       {c->T[c->cur], L.sf + L.s0 + L.sg + L.sh, (size_t)c->nT * n * c->esz}};
   for (const Part& q : parts) {
     if (!q.bytes) continue;
-    hipError_t e =
-        save ? hipMemcpyAsync(slot + q.off, q.dev, q.bytes,
-                              hipMemcpyDeviceToDevice, c->stream)
-             : hipMemcpyAsync(q.dev, slot + q.off, q.bytes,
-                              hipMemcpyDeviceToDevice, c->stream);
+    hipError_t e = hipMemcpyAsync(slot + q.off, q.dev, q.bytes,
+                                  hipMemcpyDeviceToDevice, c->stream);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -231,11 +229,11 @@ int adjoint_as(ddcc_ctx* c, int64_t nsteps, int interval, int phase,
   int rc = DDCC_OK;
   for (int64_t s = 0; s < nsteps; ++s) {
     if (s % interval == 0)
-      ACHK(copy_state(c, slot((size_t)(s / interval)), L, true), "checkpoint");
+      ACHK(save_state(c, slot((size_t)(s / interval)), L), "checkpoint");
     rc = forward_step(c);
     if (rc) return rc;
   }
-  ACHK(copy_state(c, fin, L, true), "checkpoint");
+  ACHK(save_state(c, fin, L), "checkpoint");
 
   // objective on the final state
   double sw, sm;
