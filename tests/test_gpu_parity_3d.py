@@ -87,6 +87,25 @@ def test_short_run_3d_fp32(k):
     assert drift.max() < 1e-6
 
 
+def test_long_run_3d_1000_steps():
+    """1000 steps of a 12 x 14 x 20 box (N = 2, two solid blobs, random
+    per-node angles and velocities) in FP64 and FP32 against one oracle run:
+    relative L-inf of C_i and u within 1e-10 (FP64) and 1e-5 (FP32), phase
+    mass drift within 1e-12 and 1e-6."""
+    wl = W.random_small(3, 2, (12, 14, 20), seed=34)
+    print("random 3D 12x14x20 N=2, 1000 steps", flush=True)
+    o = oracle_run(wl, 1000)
+    for precision, tol, dtol in (("fp64", 1e-10, 1e-12), ("fp32", 1e-5, 1e-6)):
+        g = gpu_run(wl, 1000, precision)
+        e = _err(g, o)
+        drift = float((np.abs(g["mass"] - g["mass0"]) /
+                       np.abs(g["mass0"])).max())
+        g["sim"].close()
+        print("%s 1000 steps" % precision, e, "drift %.1e" % drift, flush=True)
+        assert e["C"] < tol and e["u"] < tol
+        assert drift < dtol
+
+
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 1e-4)])
 def test_sphere_droplet_32(precision, tol):
     """32^3 version of the sphere / impacting-droplet case (sizes scaled by
