@@ -106,6 +106,40 @@ def test_long_run_3d_1000_steps():
         assert drift < dtol
 
 
+def _two_wall_box():
+    """12 x 10 x 24 box, N = 3, two spherical solids, each wall its own
+    psi_k and its own random per-node angles (Section 4.5 in 3D)."""
+    wl = W.random_small(3, 3, (12, 10, 24), seed=35)
+    rng = np.random.default_rng(36)
+    coords = W._grid(wl.shape)
+    walls = []
+    for c, r in (((5.0, 3.0, 4.0), 3.5), ((17.0, 7.0, 8.0), 4.0)):
+        psi_k = W.psi_from_distance(
+            W.periodic_distance(coords, c, wl.shape) - r)
+        ct_k = rng.uniform(-0.8, 0.8, size=(2,) + wl.shape)
+        walls.append((psi_k, ct_k))
+    wl.psi = walls[0][0] * walls[1][0]
+    wl.cos_theta_iN = walls[0][1]
+    wl.walls = walls
+    return wl
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 1e-5)])
+def test_two_walls_3d(precision, tol):
+    """Several walls in 3D: the library's static wetting weights
+    sum_k cos theta^k_iN |grad psi_k| (19-point stencil on each psi_k)
+    against the oracle's per-wall sum, 60 steps."""
+    wl = _two_wall_box()
+    o = oracle_run(wl, 60)
+    g = gpu_run(wl, 60, precision)
+    e = _err(g, o)
+    drift = float((np.abs(g["mass"] - g["mass0"]) / np.abs(g["mass0"])).max())
+    print("two walls 3D %s 60 steps" % precision, e, "drift %.1e" % drift,
+          flush=True)
+    assert e["C"] < tol and e["u"] < tol
+    assert drift < (1e-12 if precision == "fp64" else 1e-6)
+
+
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 1e-4)])
 def test_sphere_droplet_32(precision, tol):
     """32^3 version of the sphere / impacting-droplet case (sizes scaled by
