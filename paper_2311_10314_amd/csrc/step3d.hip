@@ -609,14 +609,24 @@ __device__ inline void step3d_node(const Coef<double>& kd, const Coef<R>& k,
   for (int c = 0; c < 3; ++c) stp(b.TB + (long long)c * n, idx, S(Tn[c]));
 }
 
-// Waves per SIMD: float64 arithmetic is capped at two (left to itself the
-// compiler gives it 256+ registers and one wave per SIMD), float arithmetic
-// at three (172 -> 168 registers with a 24-byte spill, the occupancy its LDS
-// allows; uncapped at two waves it was 17 % slower in FP32).
+// Waves per SIMD the register allocation aims at: what the LDS ring allows
+// (TY waves per workgroup, spread over the CU's four SIMDs), with float64
+// arithmetic capped at two (left to itself the compiler gives it 256+
+// registers and one wave per SIMD) and float arithmetic at three (N = 2:
+// 172 -> 168 registers with a 24-byte spill; uncapped at two waves it was
+// 17 % slower in FP32).
+template <int N, class R, int TY>
+constexpr int step3d_waves() {
+  constexpr int wgs = int((160u * 1024u) / (3u * sizeof(StepPlane<N, TY>)));
+  constexpr int lds_waves = (wgs * TY + 3) / 4;
+  constexpr int cap = sizeof(R) == 8 ? 2 : 3;
+  return lds_waves < 1 ? 1 : (lds_waves < cap ? lds_waves : cap);
+}
+
 template <int N, class LF, class LG, class Pop, class S, class R, int MODE,
           int TY>
 __global__ __launch_bounds__(TX* TY)
-__attribute__((amdgpu_waves_per_eu(sizeof(R) == 8 ? 2 : 3)))
+__attribute__((amdgpu_waves_per_eu(step3d_waves<N, R, TY>())))
 void k_step3d(Coef<double> kd, Coef<R> k, Bufs<Pop, S> b) {
   using Pl = StepPlane<N, TY>;
   constexpr int HX = TX + 2, HY = TY + 2, HN = HX * HY;
