@@ -359,22 +359,6 @@ bool all_finite(const double* a, size_t count) {
   return true;
 }
 
-template <class S>
-int upload_as(ddcc_ctx* c, const double* src, void* dst, size_t count) {
-  std::vector<S> tmp(count);
-  for (size_t i = 0; i < count; ++i) tmp[i] = S(src[i]);
-  HIPCHK(c, hipMemcpyAsync(dst, tmp.data(), count * sizeof(S),
-                           hipMemcpyHostToDevice, c->stream),
-         "hipMemcpyAsync");
-  HIPCHK(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
-  return DDCC_OK;
-}
-
-int upload(ddcc_ctx* c, const double* src, void* dst, size_t count) {
-  return c->p.precision == DDCC_FP64 ? upload_as<double>(c, src, dst, count)
-                                     : upload_as<float>(c, src, dst, count);
-}
-
 void release(ddcc_ctx* c) {
   void* ptrs[] = {c->f[0],  c->f[1],   c->f0[0],    c->f0[1], c->g[0],
                   c->g[1],  c->T[0],   c->T[1],     c->hist,  c->psi,
