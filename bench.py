@@ -367,7 +367,9 @@ def traffic_summary(fetch_dir, write_dir, precision, n):
     gib_kib = 1024.0 * 1024.0
     ff, wf = gib_kib / f_copy, gib_kib / w_copy
     per_launch = (f_step * ff + w_step * wf) * 1024.0
-    entry = {"kernel": "k_step2d<%d, %s, 0, 8>" % (N, STEP_KERNEL[precision]),
+    ty = 4 if precision == "fp64" else 8   # the library's default tiles
+    entry = {"kernel": "k_step2d<%d, %s, 0, %d>" % (N, STEP_KERNEL[precision],
+                                                     ty),
              "workload": "porous_bands_2d %dx%d N=%d" % (n, n, N),
              "kernel_hash": kernel_source_hash(),
              "dispatches": nd,

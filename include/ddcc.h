@@ -220,10 +220,19 @@ int ddcc_objective(ddcc_ctx* ctx, int phase, const double* weight, double* J);
 
 /* Kernel launch shape of the step kernel: tile (tx, ty) of nodes per
  * workgroup; 0 keeps the default. tx is 64 (one wavefront per row); ty is
- * 2, 4, 8 or 16 in 2D (default 8) and 2 or 4 in 3D (default 4). Any other
- * value returns DDCC_E_INVAL. Takes effect on the next ddcc_step; results
- * do not depend on the tile. */
+ * 2, 4, 8 or 16 in 2D (default 4 for DDCC_FP64, 8 otherwise) and 2 or 4
+ * in 3D (default 4). Any other value returns DDCC_E_INVAL. Takes effect on
+ * the next ddcc_step; results do not depend on the tile. */
 int ddcc_set_tile(ddcc_ctx* ctx, int tx, int ty);
+
+/* Times `steps` steps (after two untimed ones) with each tile height (2, 4,
+ * 8, 16 in 2D; 2, 4 in 3D) on the current state and keeps the fastest for
+ * later steps; the state and time level are restored afterwards, bit for
+ * bit. The chosen height is written to *ty_out if not NULL. Needs
+ * init_fields; allocates a temporary device copy of the state (populations,
+ * history, T) and returns DDCC_E_NOMEM, with the state and tile untouched,
+ * if that copy does not fit. Synchronises. */
+int ddcc_autotune(ddcc_ctx* ctx, int steps, int* ty_out);
 
 /* Message of the last failed call on ctx (never NULL; "" if none). */
 const char* ddcc_last_error(const ddcc_ctx* ctx);

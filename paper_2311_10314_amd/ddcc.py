@@ -84,6 +84,7 @@ def _load():
         "ddcc_load": (ctypes.c_int, [ctx, vp, ctypes.c_size_t]),
         "ddcc_sync": (ctypes.c_int, [ctx]),
         "ddcc_set_tile": (ctypes.c_int, [ctx, ctypes.c_int, ctypes.c_int]),
+        "ddcc_autotune": (ctypes.c_int, [ctx, ctypes.c_int, P(ctypes.c_int)]),
         "ddcc_adjoint": (ctypes.c_int, [ctx, ctypes.c_int64, ctypes.c_int,
                                         ctypes.c_int, dp, dp, dp, dp]),
         "ddcc_objective": (ctypes.c_int, [ctx, ctypes.c_int, dp, dp]),
@@ -135,6 +136,7 @@ ddcc_save = LIB.ddcc_save
 ddcc_load = LIB.ddcc_load
 ddcc_sync = LIB.ddcc_sync
 ddcc_set_tile = LIB.ddcc_set_tile
+ddcc_autotune = LIB.ddcc_autotune
 ddcc_adjoint = LIB.ddcc_adjoint
 ddcc_objective = LIB.ddcc_objective
 ddcc_last_error = LIB.ddcc_last_error
@@ -329,6 +331,13 @@ class Sim:
 
     def set_tile(self, tx=0, ty=0):
         self._check(LIB.ddcc_set_tile(self._h, int(tx), int(ty)))
+
+    def autotune(self, steps=5):
+        """Time each tile height on the current state, keep the fastest and
+        restore the state; returns the chosen height."""
+        ty = ctypes.c_int(0)
+        self._check(LIB.ddcc_autotune(self._h, int(steps), ctypes.byref(ty)))
+        return ty.value
 
     def adjoint(self, nsteps, interval=100, phase=0, weight=None):
         """ddcc_adjoint: J and its gradients (dJ/dcos theta_iN of shape

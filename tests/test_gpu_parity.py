@@ -83,6 +83,30 @@ def test_tile_shape_invariance_fp64(tile):
     assert np.array_equal(a["C"], b["C"]) and np.array_equal(a["u"], b["u"])
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_autotune_keeps_the_state(precision):
+    """ddcc_autotune times every tile height on the live state, keeps the
+    fastest and restores the state and time level bit for bit: stepping on
+    afterwards gives exactly what a context that never tuned gives."""
+    from paper_2311_10314_amd.ddcc import Sim
+    wl = small_cases()[1]
+    a = Sim.from_workload(wl, precision)
+    b = Sim.from_workload(wl, precision)
+    a.step(5)
+    b.step(5)
+    ty = b.autotune(3)
+    assert ty in (2, 4, 8, 16)
+    assert b.time == 5
+    a.step(10)
+    b.step(10)
+    ca, ua, pa = a.read_moments()
+    cb, ub, pb = b.read_moments()
+    assert np.array_equal(ca, cb) and np.array_equal(ua, ub)
+    assert np.array_equal(pa, pb)
+    a.close()
+    b.close()
+
+
 def test_disk_droplet_1000_steps_fp64():
     """128 x 128, N = 2, solid disk R = 30 with a droplet R = 20 at 60 deg,
     1000 steps: relative L-inf <= 1e-10, mass drift <= 1e-12."""

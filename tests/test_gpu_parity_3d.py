@@ -87,6 +87,23 @@ def test_short_run_3d_fp32(k):
     assert drift.max() < 1e-6
 
 
+def test_autotune_3d_keeps_the_state():
+    from paper_2311_10314_amd.ddcc import Sim
+    wl = cases3d()[1]
+    a = Sim.from_workload(wl, "fp32")
+    b = Sim.from_workload(wl, "fp32")
+    a.step(3)
+    b.step(3)
+    assert b.autotune(2) in (2, 4)
+    a.step(4)
+    b.step(4)
+    ca, ua, _ = a.read_moments()
+    cb, ub, _ = b.read_moments()
+    assert np.array_equal(ca, cb) and np.array_equal(ua, ub)
+    a.close()
+    b.close()
+
+
 def test_long_run_3d_1000_steps():
     """1000 steps of a 12 x 14 x 20 box (N = 2, two solid blobs, random
     per-node angles and velocities) in FP64 and FP32 against one oracle run:
