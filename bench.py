@@ -339,11 +339,14 @@ def _counter_means(csv_path, counter, precision, nphase):
     for r in rows:
         if tag in r["Kernel_Name"]:
             step.append(float(r["Counter_Value"]))
-    copies = [r for r in rows if "copyBuffer" in r["Kernel_Name"]]
+    # the 1 GiB calibration copies: the largest copy dispatches of the run
+    # (the runtime's copy kernel keeps one grid size for all large copies,
+    # so they are told apart by their counter values)
+    copies = [float(r["Counter_Value"]) for r in rows
+              if "copyBuffer" in r["Kernel_Name"]]
     if copies:
-        big = max(int(r["Grid_Size"]) for r in copies)
-        copy = [float(r["Counter_Value"]) for r in copies
-                if int(r["Grid_Size"]) == big]
+        top = max(copies)
+        copy = [v for v in copies if v >= 0.9 * top]
     if not step or not copy or max(copy) < 1.0e5:
         raise SystemExit("%s: no %s dispatches of the step kernel or of the "
                          "1 GiB copy (run with --copy-calibration)"
