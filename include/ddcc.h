@@ -175,8 +175,30 @@ int ddcc_save(ddcc_ctx* ctx, void* buf, size_t* bytes);
 /* Restores a checkpoint written by ddcc_save for identical ddcc_params. */
 int ddcc_load(ddcc_ctx* ctx, const void* buf, size_t bytes);
 
-/* Waits for all work queued on the context stream. */
+/* Waits for all work queued on the context stream. With periodic
+ * diagnostics on (ddcc_set_diagnostics), returns DDCC_E_NONFINITE once a
+ * check has seen a NaN or Inf population (the step is in the message). */
 int ddcc_sync(ddcc_ctx* ctx);
+
+/* Periodic conservation diagnostics inside the step stream: every `every`
+ * time levels (t % every == 0, counted by ddcc_step) the per-phase masses
+ * sum_x sum_p f^i_p of ddcc_mass are summed on the device, in float64, and
+ * a sticky flag records the first level at which a population was not
+ * finite, without a host synchronisation. The paper's scheme conserves
+ * each phase's mass exactly (sum_p F^i_p = 0, sum_p f^i,eq_p = phi C_i;
+ * Section 3), so the masses are a check of the run. every = 0 turns the
+ * checks off (the default); every < 0 returns DDCC_E_INVAL. Setting it,
+ * ddcc_init_fields and ddcc_load clear the record. Allocates two small
+ * device buffers on first use. Synchronises. */
+int ddcc_set_diagnostics(ddcc_ctx* ctx, int every);
+
+/* The record of the periodic checks: the masses of the last check (NaN if
+ * none has run yet) into mass[nphase] (may be NULL), its time level into
+ * *t_checked (-1 if none), and the first level whose check saw a
+ * non-finite population into *t_nonfinite (-1 if none). DDCC_E_STATE if
+ * the checks are off. Synchronises. */
+int ddcc_diagnostics(ddcc_ctx* ctx, double* mass, int64_t* t_checked,
+                     int64_t* t_nonfinite);
 
 /* ---- Adjoint (reverse-time) sweep ------------------------------------------
  * Gradient of a phase-weighted objective of the state after nsteps steps,

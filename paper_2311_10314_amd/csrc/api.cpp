@@ -362,10 +362,45 @@ bool all_finite(const double* a, size_t count) {
 void release(ddcc_ctx* c) {
   void* ptrs[] = {c->f[0],  c->f[1],   c->f0[0],    c->f0[1], c->g[0],
                   c->g[1],  c->T[0],   c->T[1],     c->hist,  c->psi,
-                  c->wet,   c->staging, c->partial, c->bad,  c->work};
+                  c->wet,   c->staging, c->partial, c->bad,  c->work,
+                  c->diag_partial, c->diag_bad, c->diag_first};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+}
+
+// Launch the per-phase population sums of the current state into
+// partial[block * N + i] with non-finite flags bad[block].
+hipError_t mass_into(ddcc_ctx* c, double* partial, int* bad) {
+  const int N = c->p.nphase;
+  const void* f = c->f[c->cur];
+  const double* f0 = c->f0[c->cur];
+  switch (c->p.precision) {
+    case DDCC_FP64:
+      return launch_mass(f0, static_cast<const double*>(f), N, c->Qf, c->n,
+                         c->n, partial, bad, c->mass_blocks, c->stream);
+    case DDCC_FP16:
+      return launch_mass(f0, static_cast<const _Float16*>(f), N, c->Qf, c->n,
+                         c->n, partial, bad, c->mass_blocks, c->stream);
+    case DDCC_BF16:
+      return launch_mass(f0, static_cast<const __bf16*>(f), N, c->Qf, c->n,
+                         c->n, partial, bad, c->mass_blocks, c->stream);
+    default:
+      return launch_mass(f0, static_cast<const float*>(f), N, c->Qf, c->n,
+                         c->n, partial, bad, c->mass_blocks, c->stream);
+  }
+}
+
+// Clear the record of the periodic checks (new state or new setting).
+int diag_reset(ddcc_ctx* c) {
+  c->diag_t = -1;
+  if (!c->diag_first) return DDCC_OK;
+  const long long none = -1;
+  HIPCHK(c, hipMemcpyAsync(c->diag_first, &none, sizeof(none),
+                           hipMemcpyHostToDevice, c->stream),
+         "clear diagnostics");
+  HIPCHK(c, hipStreamSynchronize(c->stream), "sync");
+  return DDCC_OK;
 }
 
 struct SaveHeader {
@@ -599,7 +634,7 @@ static int init_fields_common(ddcc_ctx* c, const double* C, const double* u,
   if (e != hipSuccess) return hip_fail(c, e, "init kernel");
   c->fields_ok = true;
   c->t = 0;
-  return DDCC_OK;
+  return diag_reset(c);
 }
 
 int ddcc_init_fields(ddcc_ctx* c, const double* C, const double* u,
@@ -652,6 +687,14 @@ int ddcc_step(ddcc_ctx* c, int64_t nsteps) {
     if (e != hipSuccess) return hip_fail(c, e, "step kernel");
     c->cur ^= 1;
     ++c->t;
+    if (c->diag_every > 0 && c->t % c->diag_every == 0) {
+      e = mass_into(c, c->diag_partial, c->diag_bad);
+      if (e == hipSuccess)
+        e = launch_sticky(c->diag_bad, c->mass_blocks, c->diag_first,
+                          (long long)c->t, c->stream);
+      if (e != hipSuccess) return hip_fail(c, e, "diagnostics");
+      c->diag_t = c->t;
+    }
   }
   return DDCC_OK;
 }
@@ -702,26 +745,7 @@ int ddcc_mass(ddcc_ctx* c, double* mass) {
   if (!c || !mass) return fail(c, DDCC_E_INVAL, "NULL argument");
   if (!c->fields_ok) return fail(c, DDCC_E_STATE, "init_fields first");
   const int N = c->p.nphase;
-  hipError_t e;
-  const void* f = c->f[c->cur];
-  const double* f0 = c->f0[c->cur];
-  switch (c->p.precision) {
-    case DDCC_FP64:
-      e = launch_mass(f0, static_cast<const double*>(f), N, c->Qf, c->n, c->n,
-                      c->partial, c->bad, c->mass_blocks, c->stream);
-      break;
-    case DDCC_FP16:
-      e = launch_mass(f0, static_cast<const _Float16*>(f), N, c->Qf, c->n, c->n,
-                      c->partial, c->bad, c->mass_blocks, c->stream);
-      break;
-    case DDCC_BF16:
-      e = launch_mass(f0, static_cast<const __bf16*>(f), N, c->Qf, c->n, c->n,
-                      c->partial, c->bad, c->mass_blocks, c->stream);
-      break;
-    default:
-      e = launch_mass(f0, static_cast<const float*>(f), N, c->Qf, c->n, c->n,
-                      c->partial, c->bad, c->mass_blocks, c->stream);
-  }
+  const hipError_t e = mass_into(c, c->partial, c->bad);
   if (e != hipSuccess) return hip_fail(c, e, "mass kernel");
   std::vector<double> part((size_t)c->mass_blocks * N);
   std::vector<int> bad(c->mass_blocks);
@@ -836,12 +860,66 @@ int ddcc_load(ddcc_ctx* c, const void* buf, size_t bytes) {
   HIPCHK(c, hipStreamSynchronize(c->stream), "sync");
   c->t = h.t;
   c->fields_ok = true;
-  return DDCC_OK;
+  return diag_reset(c);
 }
 
 int ddcc_sync(ddcc_ctx* c) {
   if (!c) return DDCC_E_INVAL;
   HIPCHK(c, hipStreamSynchronize(c->stream), "sync");
+  if (c->diag_every > 0) {
+    long long first = -1;
+    HIPCHK(c, hipMemcpy(&first, c->diag_first, sizeof(first),
+                        hipMemcpyDeviceToHost),
+           "read diagnostics");
+    if (first >= 0)
+      return fail(c, DDCC_E_NONFINITE,
+                  "non-finite population found by the check at step " +
+                      std::to_string(first));
+  }
+  return DDCC_OK;
+}
+
+int ddcc_set_diagnostics(ddcc_ctx* c, int every) {
+  if (!c) return DDCC_E_INVAL;
+  if (every < 0) return fail(c, DDCC_E_INVAL, "every < 0");
+  if (every > 0 && !c->diag_first) {
+    const int N = c->p.nphase;
+    HIPCHK(c, hipMalloc(&c->diag_partial,
+                        (size_t)c->mass_blocks * N * sizeof(double)),
+           "hipMalloc diagnostics");
+    HIPCHK(c, hipMalloc(&c->diag_bad, (size_t)c->mass_blocks * sizeof(int)),
+           "hipMalloc diagnostics");
+    HIPCHK(c, hipMalloc(&c->diag_first, sizeof(long long)), "hipMalloc diagnostics");
+  }
+  HIPCHK(c, hipStreamSynchronize(c->stream), "sync");
+  c->diag_every = every;
+  return diag_reset(c);
+}
+
+int ddcc_diagnostics(ddcc_ctx* c, double* mass, int64_t* t_checked,
+                     int64_t* t_nonfinite) {
+  if (!c) return DDCC_E_INVAL;
+  if (c->diag_every <= 0)
+    return fail(c, DDCC_E_STATE, "diagnostics are off (ddcc_set_diagnostics)");
+  const int N = c->p.nphase;
+  std::vector<double> part((size_t)c->mass_blocks * N);
+  long long first = -1;
+  HIPCHK(c, hipStreamSynchronize(c->stream), "sync");
+  if (c->diag_t >= 0 && mass)
+    HIPCHK(c, hipMemcpy(part.data(), c->diag_partial,
+                        part.size() * sizeof(double), hipMemcpyDeviceToHost),
+           "read diagnostics");
+  HIPCHK(c, hipMemcpy(&first, c->diag_first, sizeof(first),
+                      hipMemcpyDeviceToHost),
+         "read diagnostics");
+  if (mass)
+    for (int i = 0; i < N; ++i) {
+      double sum = 0.0;
+      for (int b = 0; b < c->mass_blocks; ++b) sum += part[(size_t)b * N + i];
+      mass[i] = c->diag_t >= 0 ? sum : std::nan("");
+    }
+  if (t_checked) *t_checked = c->diag_t;
+  if (t_nonfinite) *t_nonfinite = first;
   return DDCC_OK;
 }
 

@@ -38,6 +38,12 @@ struct ddcc_ctx {
   int nwalls = 0;  // walls of the current geometry
   int64_t t = 0;
   int tile_x = 64, tile_y = 8;
+  // periodic in-stream diagnostics (ddcc_set_diagnostics)
+  int diag_every = 0;
+  int64_t diag_t = -1;          // time level of the last check
+  double* diag_partial = nullptr;
+  int* diag_bad = nullptr;
+  long long* diag_first = nullptr;  // first level that saw a non-finite value
   std::string err;
   Coef<double> kd{};
   Coef<float> kf{};

@@ -114,6 +114,10 @@ hipError_t launch_mass(const double* f0, const Pop* f, int nphase, int Q,
                        long long n, long long stride_n, double* partial,
                        int* bad, int nblocks, hipStream_t st);
 
+// *first = t if any of bad[0 .. nb) is set and *first < 0 (one wave).
+hipError_t launch_sticky(const int* bad, int nb, long long* first,
+                         long long t, hipStream_t st);
+
 // dst[i] = S(src[i]) for i < count.
 template <class S>
 hipError_t launch_convert(const double* src, S* dst, long long count,

@@ -60,6 +60,17 @@ __global__ __launch_bounds__(kMassThreads) void k_mass(const double* f0,
   }
 }
 
+// One wave: if any of the nb block flags is set and *first is still
+// negative, *first = t (the time level of the first check that saw a
+// non-finite population).
+__global__ __launch_bounds__(64) void k_sticky(const int* bad, int nb,
+                                               long long* first, long long t) {
+  int b = 0;
+  for (int i = threadIdx.x; i < nb; i += 64) b |= bad[i];
+  for (int off = 32; off > 0; off >>= 1) b |= __shfl_xor(b, off);
+  if (threadIdx.x == 0 && b && *first < 0) *first = t;
+}
+
 template <class S>
 __global__ void k_convert(const double* src, S* dst, long long count) {
   const long long stride = (long long)gridDim.x * blockDim.x;
@@ -138,6 +149,12 @@ template hipError_t launch_wet_field<double>(const double*, const double*, int,
 template hipError_t launch_wet_field<float>(const double*, const double*, int,
                                             int, int, int, int, float*, float*,
                                             long long, long long, hipStream_t);
+
+hipError_t launch_sticky(const int* bad, int nb, long long* first,
+                         long long t, hipStream_t st) {
+  hipLaunchKernelGGL(k_sticky, dim3(1), dim3(64), 0, st, bad, nb, first, t);
+  return hipGetLastError();
+}
 
 hipError_t launch_fill_u32(unsigned* dst, unsigned v, long long count,
                            hipStream_t st) {

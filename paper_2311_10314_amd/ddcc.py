@@ -85,6 +85,9 @@ def _load():
         "ddcc_sync": (ctypes.c_int, [ctx]),
         "ddcc_set_tile": (ctypes.c_int, [ctx, ctypes.c_int, ctypes.c_int]),
         "ddcc_autotune": (ctypes.c_int, [ctx, ctypes.c_int, P(ctypes.c_int)]),
+        "ddcc_set_diagnostics": (ctypes.c_int, [ctx, ctypes.c_int]),
+        "ddcc_diagnostics": (ctypes.c_int, [ctx, dp, P(ctypes.c_int64),
+                                            P(ctypes.c_int64)]),
         "ddcc_adjoint": (ctypes.c_int, [ctx, ctypes.c_int64, ctypes.c_int,
                                         ctypes.c_int, dp, dp, dp, dp]),
         "ddcc_objective": (ctypes.c_int, [ctx, ctypes.c_int, dp, dp]),
@@ -137,6 +140,8 @@ ddcc_load = LIB.ddcc_load
 ddcc_sync = LIB.ddcc_sync
 ddcc_set_tile = LIB.ddcc_set_tile
 ddcc_autotune = LIB.ddcc_autotune
+ddcc_set_diagnostics = LIB.ddcc_set_diagnostics
+ddcc_diagnostics = LIB.ddcc_diagnostics
 ddcc_adjoint = LIB.ddcc_adjoint
 ddcc_objective = LIB.ddcc_objective
 ddcc_last_error = LIB.ddcc_last_error
@@ -331,6 +336,21 @@ class Sim:
 
     def set_tile(self, tx=0, ty=0):
         self._check(LIB.ddcc_set_tile(self._h, int(tx), int(ty)))
+
+    def set_diagnostics(self, every):
+        """Per-phase masses and a non-finite check every `every` steps,
+        inside the step stream (0: off)."""
+        self._check(LIB.ddcc_set_diagnostics(self._h, int(every)))
+
+    def diagnostics(self):
+        """(masses of the last check, its step, first step whose check saw
+        a non-finite population or -1)."""
+        m = np.empty(self.nphase)
+        tc = ctypes.c_int64(0)
+        tn = ctypes.c_int64(0)
+        self._check(LIB.ddcc_diagnostics(self._h, _dptr(m), ctypes.byref(tc),
+                                         ctypes.byref(tn)))
+        return m, tc.value, tn.value
 
     def autotune(self, steps=5):
         """Time each tile height on the current state, keep the fastest and

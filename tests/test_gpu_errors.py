@@ -107,3 +107,57 @@ def test_non_finite_population_is_reported_by_the_mass_check():
     s.load(buf)                            # a good state clears it
     assert np.all(np.isfinite(s.mass()))
     s.close()
+
+
+def test_periodic_diagnostics_record_the_masses_of_the_checked_levels():
+    """Checks every 5 steps inside the step stream: after 23 steps the last
+    check is the level 20, and its masses equal ddcc_mass of a context
+    stepped to 20 (same kernel, same block order); phase mass is
+    conserved between checks."""
+    d = _codes()
+    wl = W.random_small(2, 3, (37, 100), seed=2)
+    s = d.Sim.from_workload(wl, "fp64")
+    _expect(d.DDCC_E_STATE, s.diagnostics)             # off by default
+    _expect(d.DDCC_E_INVAL, s.set_diagnostics, -1)
+    s.set_diagnostics(5)
+    m, tc, tn = s.diagnostics()
+    assert tc == -1 and tn == -1 and np.all(np.isnan(m))
+    s.step(23)
+    s.sync()
+    m, tc, tn = s.diagnostics()
+    assert tc == 20 and tn == -1
+    ref = d.Sim.from_workload(wl, "fp64")
+    m0 = ref.mass()
+    ref.step(20)
+    assert np.array_equal(m, ref.mass())
+    assert np.abs(m - m0).max() <= 1e-12 * np.abs(m0).max()
+    s.set_diagnostics(0)
+    _expect(d.DDCC_E_STATE, s.diagnostics)
+    s.close()
+    ref.close()
+
+
+def test_periodic_diagnostics_flag_a_non_finite_state():
+    """A NaN in the loaded state is seen by the first check; ddcc_sync then
+    returns DDCC_E_NONFINITE naming the step, until a good state is
+    loaded."""
+    d = _codes()
+    wl = W.random_small(2, 2, (20, 70), seed=1)
+    s = d.Sim.from_workload(wl, "fp32")
+    good = s.save()
+    npop = wl.nphase * 9 * wl.nodes
+    off = 56 + npop * 4 + 8 * 77           # rest plane (float64), node 77
+    bad = good.copy()
+    bad[off:off + 8] = np.frombuffer(np.array([np.inf]).tobytes(), np.uint8)
+    s.set_diagnostics(2)
+    s.load(bad)
+    s.step(5)
+    e = _expect(d.DDCC_E_NONFINITE, s.sync)
+    assert "step 2" in str(e)
+    _, tc, tn = s.diagnostics()
+    assert tc == 4 and tn == 2
+    s.load(good)
+    s.step(4)
+    s.sync()
+    assert s.diagnostics()[2] == -1
+    s.close()
