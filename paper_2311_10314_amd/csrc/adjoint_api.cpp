@@ -1,7 +1,9 @@
 // Host side of ddcc_adjoint (include/ddcc.h): forward sweep with periodic
 // checkpoints, objective and seed, reverse sweep segment by segment
 // (recomputing each segment's states from its checkpoint, the step kernel
-// writing each state straight into its slot), final gradients.
+// writing each state straight into its slot), final gradients. The states
+// of the next segment are recomputed on a second stream while the reverse
+// sweep runs over the current one, into the other of two segment buffers.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -29,6 +31,26 @@ struct DevMem {
   template <class T>
   T* as(size_t byte_off = 0) const {
     return reinterpret_cast<T*>(static_cast<char*>(p) + byte_off);
+  }
+};
+
+// A second stream (default priority) and the events that order the two
+// segment buffers between it and the context stream; released on return.
+struct Pipe {
+  hipStream_t aux = nullptr;
+  hipEvent_t ready[2] = {nullptr, nullptr}, freed[2] = {nullptr, nullptr};
+  hipEvent_t start = nullptr;
+  ~Pipe() {
+    if (aux) (void)hipStreamSynchronize(aux);
+    for (hipEvent_t e : {ready[0], ready[1], freed[0], freed[1], start})
+      if (e) (void)hipEventDestroy(e);
+    if (aux) (void)hipStreamDestroy(aux);
+  }
+  hipError_t init() {
+    hipError_t e = hipStreamCreateWithFlags(&aux, hipStreamNonBlocking);
+    for (hipEvent_t* ev : {&ready[0], &ready[1], &freed[0], &freed[1], &start})
+      if (e == hipSuccess) e = hipEventCreateWithFlags(ev, hipEventDisableTiming);
+    return e;
   }
 };
 
@@ -103,11 +125,11 @@ const Coef<float>& coef_of<float>(const ddcc_ctx* c) {
 // (the history is updated in place, so it is copied over first).
 template <class S>
 hipError_t step_between(ddcc_ctx* c, const char* from, char* to,
-                        const Layout& L) {
+                        const Layout& L, hipStream_t st) {
   const size_t oh = L.sf + L.s0 + L.sg;
   const size_t sh = (size_t)c->nhist * (size_t)c->n * c->esz;
   hipError_t e = hipMemcpyAsync(to + oh, from + oh, sh, hipMemcpyDeviceToDevice,
-                                c->stream);
+                                st);
   if (e != hipSuccess) return e;
   Bufs<S, S> b{};
   const AdjFwd<S> a = view<S>(from, L);
@@ -123,7 +145,7 @@ hipError_t step_between(ddcc_ctx* c, const char* from, char* to,
   b.psi = static_cast<const S*>(c->psi);
   b.wet = static_cast<const S*>(c->wet);
   return launch_2d<S, S, S>(c->p.nphase, MODE_STEP, c->kd, coef_of<S>(c), b,
-                            c->tile_y, c->stream);
+                            c->tile_y, st);
 }
 
 int forward_step(ddcc_ctx* c) {
@@ -179,14 +201,14 @@ int adjoint_as(ddcc_ctx* c, int64_t nsteps, int interval, int phase,
   const Layout L = state_layout(c);
   const int64_t nck = (nsteps + interval - 1) / interval;
   const int64_t seg = nsteps < interval ? nsteps : interval;
-  const size_t slots = (size_t)(nck + seg + 1);
+  const size_t slots = (size_t)(nck + 2 * seg + 1);
 
   DevMem store, adj, work, grads, misc;
   ACHK(store.alloc(slots * L.total), "hipMalloc checkpoints");
   auto slot = [&](size_t i) { return store.as<char>(i * L.total); };
   char* ck0 = slot(0);
-  char* seg0 = slot((size_t)nck);
-  char* fin = slot((size_t)(nck + seg));
+  char* segbuf[2] = {slot((size_t)nck), slot((size_t)(nck + seg))};
+  char* fin = slot((size_t)(nck + 2 * seg));
 
   const size_t sfl = (size_t)N * 9 * n, sgl = 9 * n, shl = (size_t)c->nhist * n;
   const size_t sal = (size_t)adj_planes(N) * n;
@@ -247,19 +269,40 @@ int adjoint_as(ddcc_ctx* c, int64_t nsteps, int interval, int phase,
   ACHK(hipMemsetAsync(adj.p, 0, adj_count * sizeof(R), c->stream), "clear adjoint");
   ACHK(launch_adj_seed(c->kd, phase, wgt, J, sm, lf[0], c->stream), "seed kernel");
 
-  // reverse sweep, one segment at a time
-  int la = 0;
-  for (int64_t sg = nck - 1; sg >= 0; --sg) {
+  // reverse sweep, one segment at a time. Segment sg's states are in
+  // segbuf[(nck - 1 - sg) % 2]; while the context stream runs the reverse
+  // steps over them, the second stream recomputes segment sg - 1 into the
+  // other buffer, once the reverse sweep of segment sg + 1 has released it.
+  Pipe pp;
+  ACHK(pp.init(), "adjoint streams");
+  auto recompute = [&](int64_t sg, char* dst) -> hipError_t {
     const int64_t s0 = sg * interval;
     const int64_t s1 = s0 + interval < nsteps ? s0 + interval : nsteps;
-    // the segment's states, each written by the step straight into its slot
-    ACHK(hipMemcpyAsync(seg0, ck0 + (size_t)sg * L.total, L.total,
-                        hipMemcpyDeviceToDevice, c->stream),
-         "restore checkpoint");
-    for (int64_t s = s0; s < s1 - 1; ++s) {
-      char* from = seg0 + (size_t)(s - s0) * L.total;
-      ACHK(step_between<S>(c, from, from + L.total, L), "step kernel");
+    hipError_t e = hipMemcpyAsync(dst, ck0 + (size_t)sg * L.total, L.total,
+                                  hipMemcpyDeviceToDevice, pp.aux);
+    for (int64_t s = s0; s < s1 - 1 && e == hipSuccess; ++s) {
+      char* from = dst + (size_t)(s - s0) * L.total;
+      e = step_between<S>(c, from, from + L.total, L, pp.aux);
     }
+    return e;
+  };
+  // the checkpoints were written on the context stream
+  ACHK(hipEventRecord(pp.start, c->stream), "event");
+  ACHK(hipStreamWaitEvent(pp.aux, pp.start, 0), "event");
+  ACHK(recompute(nck - 1, segbuf[0]), "step kernel");
+  ACHK(hipEventRecord(pp.ready[0], pp.aux), "event");
+  int la = 0;
+  for (int64_t sg = nck - 1; sg >= 0; --sg) {
+    const int b = (int)((nck - 1 - sg) % 2);
+    if (sg > 0) {
+      if (sg + 1 <= nck - 1)
+        ACHK(hipStreamWaitEvent(pp.aux, pp.freed[b ^ 1], 0), "event");
+      ACHK(recompute(sg - 1, segbuf[b ^ 1]), "step kernel");
+      ACHK(hipEventRecord(pp.ready[b ^ 1], pp.aux), "event");
+    }
+    ACHK(hipStreamWaitEvent(c->stream, pp.ready[b], 0), "event");
+    const int64_t s0 = sg * interval;
+    const int64_t s1 = s0 + interval < nsteps ? s0 + interval : nsteps;
     for (int64_t s = s1 - 1; s >= s0; --s) {
       AdjBufs<R> ab;
       ab.lfB = lf[la];
@@ -274,12 +317,13 @@ int adjoint_as(ddcc_ctx* c, int64_t nsteps, int interval, int phase,
       ab.gpsi = gpsi;
       ab.ggpsi = ggpsi;
       ACHK(launch_adj_step<S>(N, c->kd,
-                              view<S>(seg0 + (size_t)(s - s0) * L.total, L),
+                              view<S>(segbuf[b] + (size_t)(s - s0) * L.total, L),
                               static_cast<const S*>(c->psi),
                               static_cast<const S*>(c->wet), w, ab, c->stream),
            "adjoint step kernels");
       la ^= 1;
     }
+    ACHK(hipEventRecord(pp.freed[b], c->stream), "event");
   }
 
   ACHK(launch_adj_finish<S>(c->kd, N - 1, static_cast<const S*>(c->psi),
