@@ -217,8 +217,10 @@ int ddcc_diagnostics(ddcc_ctx* ctx, double* mass, int64_t* t_checked,
  * Runs the nsteps forward steps (checkpointing the state every `interval`
  * steps on the device), evaluates J, then sweeps back one segment of
  * `interval` steps at a time, recomputing the segment's states from its
- * checkpoint. Device memory: about (nsteps / interval + interval + 1)
- * states plus a few adjoint states, released on return. On success the
+ * checkpoint; the next segment is recomputed on a second stream of
+ * default priority while the current one is swept. Device memory: about
+ * (nsteps / interval + 2 interval + 1) states plus a few adjoint states,
+ * released on return. On success the
  * context is left at the final level (time advanced by nsteps).
  *
  * weight     host [ny][nx] float64, finite (the w above)
