@@ -287,6 +287,15 @@ typedef struct ddcc_batch ddcc_batch;
 int ddcc_batch_create(const ddcc_params* params, int count, const int* nx,
                       const int* ny, void* hip_stream, ddcc_batch** out);
 
+/* Method parameters of instance i alone (parameter samples: densities,
+ * viscosities, surface tensions, mobility, rates, forces ...), replacing the
+ * batch's for that instance; dim, nphase, the lattices and the precision
+ * must be the batch's (DDCC_E_INVAL otherwise), and the parameters are
+ * validated as in ddcc_create. Call it before the instance's
+ * ddcc_batch_init_fields (the initial equilibrium uses them); it may also be
+ * called later, and then takes effect on the next step. Synchronises. */
+int ddcc_batch_set_params(ddcc_batch* b, int i, const ddcc_params* params);
+
 /* Geometry of instance i: psi [ny_i][nx_i] in [0, 1] and the N-1 wetting
  * cosines cos theta_iN [N-1][ny_i][nx_i] in [-1, 1] (NULL: 90 degrees).
  * Resets the instance's fields (init_fields again before stepping). */

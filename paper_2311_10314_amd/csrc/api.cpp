@@ -1069,6 +1069,10 @@ struct ddcc_batch {
   std::string err;
   Coef<double> kd{};
   Coef<float> kf{};
+  // device tables of every instance's coefficients (the batch parameters,
+  // or an instance's own ones from ddcc_batch_set_params)
+  Coef<double>* kds = nullptr;
+  Coef<float>* kfs = nullptr;
 };
 
 namespace {
@@ -1107,7 +1111,7 @@ void batch_release(ddcc_batch* b) {
   void* ptrs[] = {b->f[0],   b->f[1], b->f0[0],    b->f0[1],    b->g[0],
                   b->g[1],   b->T[0], b->T[1],     b->hist,     b->psi,
                   b->wet,    b->staging, b->partial, b->bad, b->tiles,
-                  b->insts,  b->counters};
+                  b->insts,  b->counters, b->kds, b->kfs};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
@@ -1173,7 +1177,7 @@ Bufs<Pop, S> batch_bufs(ddcc_batch* b, int mode) {
 }
 
 template <class Pop, class S, class R>
-hipError_t batch_launch_as(ddcc_batch* b, const Coef<R>& k, int mode,
+hipError_t batch_launch_as(ddcc_batch* b, const Coef<R>* k, int mode,
                            unsigned t0, unsigned nt, unsigned* counter,
                            const double* inC, const double* inU,
                            const double* inP, double* oC, double* oU,
@@ -1188,7 +1192,7 @@ hipError_t batch_launch_as(ddcc_batch* b, const Coef<R>& k, int mode,
   long long nb = b->blocks;
   if (nb > nt) nb = nt;
   if (nb < 1) nb = 1;
-  return launch_2d_batch<Pop, S, R>(b->p.nphase, mode, b->kd, k, r,
+  return launch_2d_batch<Pop, S, R>(b->p.nphase, mode, b->kds, k, r,
                                     b->tiles + t0, b->insts, nt, counter,
                                     (int)nb, b->ty, b->stream);
 }
@@ -1203,16 +1207,16 @@ hipError_t batch_launch(ddcc_batch* b, int mode, unsigned t0, unsigned nt,
   if (e != hipSuccess) return e;
   switch (b->p.precision) {
     case DDCC_FP64:
-      return batch_launch_as<double, double>(b, b->kd, mode, t0, nt, counter,
+      return batch_launch_as<double, double>(b, b->kds, mode, t0, nt, counter,
                                              inC, inU, inP, oC, oU, oP);
     case DDCC_FP16:
-      return batch_launch_as<_Float16, float>(b, b->kf, mode, t0, nt, counter,
+      return batch_launch_as<_Float16, float>(b, b->kfs, mode, t0, nt, counter,
                                               inC, inU, inP, oC, oU, oP);
     case DDCC_BF16:
-      return batch_launch_as<__bf16, float>(b, b->kf, mode, t0, nt, counter,
+      return batch_launch_as<__bf16, float>(b, b->kfs, mode, t0, nt, counter,
                                             inC, inU, inP, oC, oU, oP);
     default:
-      return batch_launch_as<float, float>(b, b->kf, mode, t0, nt, counter,
+      return batch_launch_as<float, float>(b, b->kfs, mode, t0, nt, counter,
                                            inC, inU, inP, oC, oU, oP);
   }
 }
@@ -1257,22 +1261,22 @@ int batch_capture(ddcc_batch* b) {
   for (int s = 0; s < b->graph_steps && e == hipSuccess; ++s) {
     switch (b->p.precision) {
       case DDCC_FP64:
-        e = batch_launch_as<double, double>(b, b->kd, MODE_STEP, 0, b->ntiles,
+        e = batch_launch_as<double, double>(b, b->kds, MODE_STEP, 0, b->ntiles,
                                             b->counters + s, nullptr, nullptr,
                                             nullptr, nullptr, nullptr, nullptr);
         break;
       case DDCC_FP16:
-        e = batch_launch_as<_Float16, float>(b, b->kf, MODE_STEP, 0, b->ntiles,
+        e = batch_launch_as<_Float16, float>(b, b->kfs, MODE_STEP, 0, b->ntiles,
                                              b->counters + s, nullptr, nullptr,
                                              nullptr, nullptr, nullptr, nullptr);
         break;
       case DDCC_BF16:
-        e = batch_launch_as<__bf16, float>(b, b->kf, MODE_STEP, 0, b->ntiles,
+        e = batch_launch_as<__bf16, float>(b, b->kfs, MODE_STEP, 0, b->ntiles,
                                            b->counters + s, nullptr, nullptr,
                                            nullptr, nullptr, nullptr, nullptr);
         break;
       default:
-        e = batch_launch_as<float, float>(b, b->kf, MODE_STEP, 0, b->ntiles,
+        e = batch_launch_as<float, float>(b, b->kfs, MODE_STEP, 0, b->ntiles,
                                           b->counters + s, nullptr, nullptr,
                                           nullptr, nullptr, nullptr, nullptr);
     }
@@ -1380,12 +1384,54 @@ int ddcc_batch_create(const ddcc_params* p, int count, const int* nx,
       e = hipMemcpy(b->insts, ins.data(), count * sizeof(BatchInst),
                     hipMemcpyHostToDevice);
   }
+  if (e == hipSuccess) {
+    const std::vector<Coef<double>> vd(count, b->kd);
+    const std::vector<Coef<float>> vf(count, b->kf);
+    e = hipMalloc(&b->kds, count * sizeof(Coef<double>));
+    if (e == hipSuccess) e = hipMalloc(&b->kfs, count * sizeof(Coef<float>));
+    if (e == hipSuccess)
+      e = hipMemcpy(b->kds, vd.data(), count * sizeof(Coef<double>),
+                    hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+      e = hipMemcpy(b->kfs, vf.data(), count * sizeof(Coef<float>),
+                    hipMemcpyHostToDevice);
+  }
   if (e != hipSuccess || build_tiles(b, 8) != DDCC_OK) {
     batch_release(b);
     delete b;
     return e == hipErrorOutOfMemory ? DDCC_E_NOMEM : DDCC_E_HIP;
   }
   *out = b;
+  return DDCC_OK;
+}
+
+int ddcc_batch_set_params(ddcc_batch* b, int i, const ddcc_params* p) {
+  int rc = batch_check(b, i);
+  if (rc) return rc;
+  if (!p) return bfail(b, DDCC_E_INVAL, "params is NULL");
+  if (p->dim != b->p.dim || p->nphase != b->p.nphase ||
+      p->lattice_f != b->p.lattice_f || p->lattice_g != b->p.lattice_g ||
+      p->precision != b->p.precision)
+    return bfail(b, DDCC_E_INVAL,
+                 "dim, nphase, lattices and precision must be the batch's");
+  ddcc_params q = *p;
+  q.nx = b->nx[i];
+  q.ny = b->ny[i];
+  q.nz = 1;
+  std::string msg;
+  rc = validate(&q, msg);
+  if (rc != DDCC_OK) return bfail(b, rc, msg);
+  Coef<double> kd;
+  Coef<float> kf;
+  fill_coef<double>(q, b->ntot, kd);
+  fill_coef<float>(q, b->ntot, kf);
+  // the tables are read by kernels on the batch stream
+  if (hipStreamSynchronize(b->stream) != hipSuccess ||
+      hipMemcpy(b->kds + i, &kd, sizeof(kd), hipMemcpyHostToDevice) !=
+          hipSuccess ||
+      hipMemcpy(b->kfs + i, &kf, sizeof(kf), hipMemcpyHostToDevice) !=
+          hipSuccess)
+    return bfail(b, DDCC_E_HIP, "copy parameters");
   return DDCC_OK;
 }
 

@@ -77,10 +77,11 @@ struct BatchInst {
 
 // One step (or initialisation, or moment read-out) of the instances whose
 // tiles are listed: a persistent launch of nblocks workgroups that drain the
-// tile queue; *counter must be zero at launch.
+// tile queue; *counter must be zero at launch. kd, k: device tables of the
+// coefficients of every instance.
 template <class Pop, class S, class R>
-hipError_t launch_2d_batch(int nphase, int mode, const Coef<double>& kd,
-                           const Coef<R>& k,
+hipError_t launch_2d_batch(int nphase, int mode, const Coef<double>* kd,
+                           const Coef<R>* k,
                            const Bufs<Pop, S>& b, const BatchTile* tiles,
                            const BatchInst* insts, unsigned ntiles,
                            unsigned* counter, int nblocks, int ty,

@@ -651,10 +651,14 @@ hipError_t launch_mode(int mode, const Coef<double>& kd, const Coef<R>& k,
 // each workgroup takes the next tile index from *counter until the queue is
 // empty, then exits. Tiles of one step are independent, so no workgroup ever
 // waits for another; the counter must be zero at launch.
+// kds / ks: the coefficients of each instance (per-instance parameters),
+// read where they are used with the instance index of the tile, which is
+// uniform, so the reads are scalar.
 template <int N, class Pop, class S, class R, int MODE, int TY>
 __global__ __launch_bounds__(TX* TY) void k_step2d_batch(
-    Coef<double> kd, Coef<R> k, Bufs<Pop, S> b, const BatchTile* tiles,
-    const BatchInst* insts, unsigned ntiles, unsigned* counter) {
+    const Coef<double>* __restrict__ kds, const Coef<R>* __restrict__ ks,
+    Bufs<Pop, S> b, const BatchTile* tiles, const BatchInst* insts,
+    unsigned ntiles, unsigned* counter) {
   __shared__ unsigned next;
   for (;;) {
     if (threadIdx.x == 0) next = atomicAdd(counter, 1u);
@@ -666,13 +670,15 @@ __global__ __launch_bounds__(TX* TY) void k_step2d_batch(
     if (t >= ntiles) break;
     const BatchTile tl = tiles[t];
     const BatchInst in = insts[tl.inst];
+    const Coef<R>& k = ks[tl.inst];
     Step2D<N, Pop, S, R, MODE, TY>::tile(
-        kd, k, b, Grid{in.nx, in.ny, k.n, unsigned(in.off)}, tl.x0, tl.y0);
+        kds[tl.inst], k, b, Grid{in.nx, in.ny, k.n, unsigned(in.off)}, tl.x0,
+        tl.y0);
   }
 }
 
 template <int N, class Pop, class S, class R, int TY>
-hipError_t launch_batch_n(int mode, const Coef<double>& kd, const Coef<R>& k,
+hipError_t launch_batch_n(int mode, const Coef<double>* kd, const Coef<R>* k,
                           const Bufs<Pop, S>& b, const BatchTile* tiles,
                           const BatchInst* insts, unsigned ntiles,
                           unsigned* counter, int nblocks, hipStream_t st) {
@@ -719,8 +725,8 @@ hipError_t launch_2d(int nphase, int mode, const Coef<double>& kd,
 }
 
 template <class Pop, class S, class R>
-hipError_t launch_2d_batch(int nphase, int mode, const Coef<double>& kd,
-                           const Coef<R>& k,
+hipError_t launch_2d_batch(int nphase, int mode, const Coef<double>* kd,
+                           const Coef<R>* k,
                            const Bufs<Pop, S>& b, const BatchTile* tiles,
                            const BatchInst* insts, unsigned ntiles,
                            unsigned* counter, int nblocks, int ty,
@@ -763,7 +769,7 @@ int batch_blocks_per_cu(int nphase, int ty) {
 
 #define DDCC_BATCH_INST(P, S, R)                                              \
   template hipError_t launch_2d_batch<P, S, R>(                               \
-      int, int, const Coef<double>&, const Coef<R>&, const Bufs<P, S>&,       \
+      int, int, const Coef<double>*, const Coef<R>*, const Bufs<P, S>&,       \
       const BatchTile*, const BatchInst*, unsigned, unsigned*, int, int,      \
       hipStream_t);                                                           \
   template int batch_blocks_per_cu<P, S, R>(int, int);

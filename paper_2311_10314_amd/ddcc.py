@@ -97,6 +97,8 @@ def _load():
         "ddcc_batch_create": (ctypes.c_int, [P(ddcc_params), ctypes.c_int,
                                              P(ctypes.c_int), P(ctypes.c_int),
                                              vp, P(vp)]),
+        "ddcc_batch_set_params": (ctypes.c_int, [vp, ctypes.c_int,
+                                                 P(ddcc_params)]),
         "ddcc_batch_init_geometry": (ctypes.c_int, [vp, ctypes.c_int, dp, dp]),
         "ddcc_batch_init_fields": (ctypes.c_int, [vp, ctypes.c_int, dp, dp,
                                                   dp]),
@@ -148,6 +150,7 @@ ddcc_last_error = LIB.ddcc_last_error
 ddcc_destroy = LIB.ddcc_destroy
 ddcc_version = LIB.ddcc_version
 ddcc_batch_create = LIB.ddcc_batch_create
+ddcc_batch_set_params = LIB.ddcc_batch_set_params
 ddcc_batch_init_geometry = LIB.ddcc_batch_init_geometry
 ddcc_batch_init_fields = LIB.ddcc_batch_init_fields
 ddcc_batch_step = LIB.ddcc_batch_step
@@ -414,15 +417,25 @@ class Batch:
 
     @classmethod
     def from_workloads(cls, wls, precision="fp32", stream=None):
-        """All workloads must share N and the method parameters."""
+        """All workloads must share N; an instance whose method parameters
+        differ from the first one's gets its own (ddcc_batch_set_params)."""
         w0 = wls[0]
         p = make_params(2, w0.shape, w0.nphase, "D2Q9", "D2Q9", precision,
                         **w0.params)
         b = cls(p, [w.shape for w in wls], stream)
         for i, w in enumerate(wls):
+            if w.params != w0.params:
+                b.set_params(i, make_params(2, w.shape, w.nphase, "D2Q9",
+                                            "D2Q9", precision, **w.params))
             b.init_geometry(i, w.psi, w.cos_theta_iN)
             b.init_fields(i, w.C0, w.u0, w.P0)
         return b
+
+    def set_params(self, i, params):
+        """Method parameters of instance i (a ddcc_params with the batch's
+        dim, N, lattices and precision); call before its init_fields."""
+        self._check(LIB.ddcc_batch_set_params(self._h, int(i),
+                                              ctypes.byref(params)))
 
     def _check(self, rc):
         if rc != DDCC_OK:

@@ -126,3 +126,61 @@ def test_batched_workload_fp32_mass_and_single():
             i, wl.shape, drift.max(), e_s), flush=True)
         assert drift.max() < 1e-6 and e_s < 1e-5
     b.close()
+
+
+def _samples():
+    """Parameter samples: the same N = 2 method with different densities,
+    viscosities, surface tension, mobility and body force per instance."""
+    return [W.random_small(2, 2, (20, 70), seed=1),
+            W.random_small(2, 2, (33, 64), seed=7, rho=[1.0, 10.0],
+                           nu=[0.05, 0.15], m0=0.02,
+                           sigma=[[0.0, 0.005], [0.005, 0.0]]),
+            W.random_small(2, 2, (9, 13), seed=4, rho=[4.0, 0.5],
+                           force=[1e-5, 0.0]),
+            W.random_small(2, 2, (64, 5), seed=8, nu=[0.3, 0.02], m0=0.1)]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_batch_parameter_samples(precision):
+    """Each instance with its own parameters (ddcc_batch_set_params) evolves
+    as a single context with those parameters (within 1e-13 in FP64, 2e-6
+    in FP32: the two kernels are compiled separately) and, in FP64, within
+    1e-10 of the oracle; with a graph step loop too."""
+    from paper_2311_10314_amd.ddcc import Batch
+    wls = _samples()
+    assert len({repr(w.params) for w in wls}) == len(wls)
+    b = Batch.from_workloads(wls, precision)
+    b.step(12)
+    b.set_graph(4)
+    b.step(8)
+    for i, wl in enumerate(wls):
+        got = b.read_moments(i)
+        single = _single(wl, 20, precision)
+        e_s = _errs(got, single)
+        print("instance %d %s: vs single %.2e" % (i, precision, e_s),
+              flush=True)
+        assert e_s < (1e-13 if precision == "fp64" else 2e-6)
+        if precision == "fp64":
+            o = oracle_run(wl, 20)
+            e = _errs(got, (o["C"], o["u"]))
+            print("instance %d: vs oracle %.2e" % (i, e), flush=True)
+            assert e < 1e-10
+    b.close()
+
+
+def test_batch_parameters_must_match_the_batch():
+    from paper_2311_10314_amd.ddcc import (DDCC_E_INVAL, Batch, DDCCError,
+                                           make_params)
+    wls = _samples()[:2]
+    b = Batch.from_workloads(wls, "fp32")
+    other = make_params(2, wls[0].shape, 3, "D2Q9", "D2Q9", "fp32",
+                        **W.random_small(2, 3, (20, 70), seed=1).params)
+    with pytest.raises(DDCCError) as e:
+        b.set_params(0, other)
+    assert e.value.code == DDCC_E_INVAL
+    bad = make_params(2, wls[0].shape, 2, "D2Q9", "D2Q9", "fp32",
+                      **dict(wls[0].params, rho=[1.0, -1.0]))
+    with pytest.raises(DDCCError) as e:
+        b.set_params(1, bad)
+    assert e.value.code == DDCC_E_INVAL
+    b.close()
