@@ -286,11 +286,14 @@ int adjoint_as(ddcc_ctx* c, int64_t nsteps, int interval, int phase,
     }
     return e;
   };
-  // the checkpoints were written on the context stream
-  ACHK(hipEventRecord(pp.start, c->stream), "event");
-  ACHK(hipStreamWaitEvent(pp.aux, pp.start, 0), "event");
-  ACHK(recompute(nck - 1, segbuf[0]), "step kernel");
-  ACHK(hipEventRecord(pp.ready[0], pp.aux), "event");
+  // the checkpoints were written on the context stream (no segment at all
+  // when nsteps = 0)
+  if (nck > 0) {
+    ACHK(hipEventRecord(pp.start, c->stream), "event");
+    ACHK(hipStreamWaitEvent(pp.aux, pp.start, 0), "event");
+    ACHK(recompute(nck - 1, segbuf[0]), "step kernel");
+    ACHK(hipEventRecord(pp.ready[0], pp.aux), "event");
+  }
   int la = 0;
   for (int64_t sg = nck - 1; sg >= 0; --sg) {
     const int b = (int)((nck - 1 - sg) % 2);

@@ -307,6 +307,9 @@ Bufs<Pop, S> bufs(ddcc_ctx* c, int mode) {
     b.fC = c->work;
     b.fmu = c->work + (size_t)c->p.nphase * c->n;
   }
+  b.coef_d = c->dkd;
+  b.coef_r = sizeof(S) == 8 ? static_cast<const void*>(c->dkd)
+                            : static_cast<const void*>(c->dkf);
   return b;
 }
 
@@ -363,7 +366,8 @@ void release(ddcc_ctx* c) {
   void* ptrs[] = {c->f[0],  c->f[1],   c->f0[0],    c->f0[1], c->g[0],
                   c->g[1],  c->T[0],   c->T[1],     c->hist,  c->psi,
                   c->wet,   c->staging, c->partial, c->bad,  c->work,
-                  c->diag_partial, c->diag_bad, c->diag_first};
+                  c->diag_partial, c->diag_bad, c->diag_first,
+                  c->dkd,   c->dkf};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
@@ -527,6 +531,12 @@ int ddcc_create(const ddcc_params* p, void* stream, ddcc_ctx** out) {
     e = hipMalloc(&c->partial,
                   (size_t)c->mass_blocks * p->nphase * sizeof(double));
   if (e == hipSuccess) e = hipMalloc(&c->bad, (size_t)c->mass_blocks * sizeof(int));
+  if (e == hipSuccess) e = hipMalloc(&c->dkd, sizeof(Coef<double>));
+  if (e == hipSuccess) e = hipMalloc(&c->dkf, sizeof(Coef<float>));
+  if (e == hipSuccess)
+    e = hipMemcpy(c->dkd, &c->kd, sizeof(Coef<double>), hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(c->dkf, &c->kf, sizeof(Coef<float>), hipMemcpyHostToDevice);
   // plane 0 of the phase buffers is never written by the kernels (the rest
   // populations live in f0): zero it so that checkpoints are deterministic
   for (int a = 0; a < 2 && e == hipSuccess; ++a)

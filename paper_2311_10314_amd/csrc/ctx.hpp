@@ -47,6 +47,8 @@ struct ddcc_ctx {
   std::string err;
   Coef<double> kd{};
   Coef<float> kf{};
+  Coef<double>* dkd = nullptr;  // device copies of kd and kf
+  Coef<float>* dkf = nullptr;
 };
 
 namespace ddcc::detail {

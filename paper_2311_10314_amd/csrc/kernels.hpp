@@ -38,6 +38,10 @@ struct Bufs {
   double* outP;
   double* fC;      // 3D work fields: C_i [N][n] and mu_i [N][n], float64
   double* fmu;
+  // device copies of the context's coefficients, Coef<double> and Coef<S>
+  // (3D step kernel: read by scalar loads instead of kernel arguments)
+  const void* coef_d;
+  const void* coef_r;
 };
 
 // A population value v written in a narrower storage type: returns the
