@@ -144,6 +144,9 @@ hipError_t step_between(ddcc_ctx* c, const char* from, char* to,
   b.TB = reinterpret_cast<S*>(to + oh + L.sh);
   b.psi = static_cast<const S*>(c->psi);
   b.wet = static_cast<const S*>(c->wet);
+  b.coef_d = c->dkd;
+  b.coef_r = sizeof(S) == 8 ? static_cast<const void*>(c->dkd)
+                            : static_cast<const void*>(c->dkf);
   return launch_2d<S, S, S>(c->p.nphase, MODE_STEP, c->kd, coef_of<S>(c), b,
                             c->tile_y, st);
 }

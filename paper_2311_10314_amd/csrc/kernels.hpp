@@ -39,7 +39,8 @@ struct Bufs {
   double* fC;      // 3D work fields: C_i [N][n] and mu_i [N][n], float64
   double* fmu;
   // device copies of the context's coefficients, Coef<double> and Coef<S>
-  // (3D step kernel: read by scalar loads instead of kernel arguments)
+  // (read by scalar loads instead of kernel arguments: the single-context
+  // 2D kernel, and the 3D step kernel for some storage types)
   const void* coef_d;
   const void* coef_r;
 };

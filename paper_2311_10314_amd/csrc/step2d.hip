@@ -595,38 +595,47 @@ struct Step2D {
   }
 };
 
+// kd, k: the context's coefficients in device memory. Passed by value the
+// two structs (about 1.5 KB) overflow the scalar registers and spill into
+// VGPR lanes; read through __restrict__ pointers they are scalar loads where
+// used (512^2 N = 3, same box: FP32 23.3 -> 22.4 us, FP64 49.2 -> 48.3 us).
 template <int N, class Pop, class S, class R, int MODE, int TY>
-__global__ __launch_bounds__(TX* TY) void k_step2d(Coef<double> kd, Coef<R> k,
-                                                    Bufs<Pop, S> b) {
-  Step2D<N, Pop, S, R, MODE, TY>::run(kd, k, b);
+__global__ __launch_bounds__(TX* TY) void k_step2d(
+    const Coef<double>* __restrict__ kd, const Coef<R>* __restrict__ k,
+    Bufs<Pop, S> b) {
+  Step2D<N, Pop, S, R, MODE, TY>::run(*kd, *k, b);
 }
 
 template <int N, class Pop, class S, class R, int MODE>
 hipError_t launch_ty(const Coef<double>& kd, const Coef<R>& k,
                      const Bufs<Pop, S>& b, int ty, hipStream_t st) {
+  (void)kd;
+  const Coef<double>* dk = static_cast<const Coef<double>*>(b.coef_d);
+  const Coef<R>* dr = static_cast<const Coef<R>*>(b.coef_r);
+  if (!dk || !dr) return hipErrorInvalidValue;
   switch (ty) {
     case 4: {
       dim3 g((k.nx + TX - 1) / TX, (k.ny + 3) / 4);
       hipLaunchKernelGGL((k_step2d<N, Pop, S, R, MODE, 4>), g, dim3(TX * 4), 0, st,
-                         kd, k, b);
+                         dk, dr, b);
       break;
     }
     case 16: {
       dim3 g((k.nx + TX - 1) / TX, (k.ny + 15) / 16);
       hipLaunchKernelGGL((k_step2d<N, Pop, S, R, MODE, 16>), g, dim3(TX * 16), 0, st,
-                         kd, k, b);
+                         dk, dr, b);
       break;
     }
     case 2: {
       dim3 g((k.nx + TX - 1) / TX, (k.ny + 1) / 2);
       hipLaunchKernelGGL((k_step2d<N, Pop, S, R, MODE, 2>), g, dim3(TX * 2), 0, st,
-                         kd, k, b);
+                         dk, dr, b);
       break;
     }
     default: {
       dim3 g((k.nx + TX - 1) / TX, (k.ny + 7) / 8);
       hipLaunchKernelGGL((k_step2d<N, Pop, S, R, MODE, 8>), g, dim3(TX * 8), 0, st,
-                         kd, k, b);
+                         dk, dr, b);
       break;
     }
   }
