@@ -612,26 +612,24 @@ __device__ inline void step3d_node(const Coef<double>& kd, const Coef<R>& k,
 }
 
 // Waves per SIMD the register allocation aims at: what the LDS ring allows
-// (TY waves per workgroup, spread over the CU's four SIMDs), with float64
-// arithmetic capped at two (left to itself the compiler gives it 256+
-// registers and one wave per SIMD) and float arithmetic at three (N = 2:
-// 172 -> 168 registers with a 24-byte spill; uncapped at two waves it was
-// 17 % slower in FP32). FP16 storage is capped at two as well (same box,
-// 256^3: 2.68 ms per step with coefficient arguments at three waves, 4.39
-// ms with arguments at two, 1.98 ms with the coefficient table at two).
-template <int N, class Pop, class R, int TY>
+// (TY waves per workgroup, spread over the CU's four SIMDs), capped at two.
+// Left to itself the compiler gives the float64 kernel 256+ registers and
+// one wave per SIMD. The float kernels were capped at three while their
+// coefficients came as arguments (at two, FP32 was 17 % slower); with the
+// coefficient table two is the faster cap (same box, 256^3 per step: FP32
+// 2.95 -> 2.86 ms, FP16 2.68 -> 1.98 ms, BF16 unchanged).
+template <int N, int TY>
 constexpr int step3d_waves() {
   constexpr int wgs = int((160u * 1024u) / (3u * sizeof(StepPlane<N, TY>)));
   constexpr int lds_waves = (wgs * TY + 3) / 4;
-  constexpr int cap =
-      sizeof(R) == 8 || std::is_same_v<Pop, _Float16> ? 2 : 3;
+  constexpr int cap = 2;
   return lds_waves < 1 ? 1 : (lds_waves < cap ? lds_waves : cap);
 }
 
 template <int N, class LF, class LG, class Pop, class S, class R, int MODE,
           int TY>
 __global__ __launch_bounds__(TX* TY)
-__attribute__((amdgpu_waves_per_eu(step3d_waves<N, Pop, R, TY>())))
+__attribute__((amdgpu_waves_per_eu(step3d_waves<N, TY>())))
 void k_step3d(Coef<double> kda, Coef<R> ka,
               const Coef<double>* __restrict__ kdp,
               const Coef<R>* __restrict__ kp, Bufs<Pop, S> b) {
@@ -639,8 +637,8 @@ void k_step3d(Coef<double> kda, Coef<R> ka,
   // into VGPR lanes; read from a device table they cost no spills but scalar
   // loads inside the z loop. Which is faster depends on the storage type
   // (same box, 256^3: table for BF16 2.79 -> 2.00 ms, FP32 3.00 -> 2.97 ms
-  // and FP16, at two waves, 2.68 -> 1.98 ms per step; arguments for FP64
-  // 5.09 vs 5.60 ms).
+  // and FP16 2.68 -> 1.98 ms per step, the last two at two waves per SIMD;
+  // arguments for FP64 5.09 vs 5.60 ms).
   constexpr bool TABLE = std::is_same_v<Pop, __bf16> ||
                          std::is_same_v<Pop, float> ||
                          std::is_same_v<Pop, _Float16>;
