@@ -304,10 +304,12 @@ struct Step2D {
     const int tid = threadIdx.x;
     const int tx = tid % TX, ty = tid / TX;
     D psiC[N], psimu_d[N], dummy[N];
-    // float arithmetic: the own node's pulled populations stay in registers
-    // from phase 1 to the collision (phase 3 would otherwise load them
-    // again, after the whole chunk's phase-1 traffic has gone through L2)
-    constexpr bool KEEP = MODE == MODE_STEP && sizeof(R) == 4;
+    // The own node's pulled populations stay in registers from phase 1 to
+    // the collision (phase 3 would otherwise load them again, after the
+    // whole chunk's phase-1 traffic has gone through L2). In float64 that
+    // takes the kernel to 187 VGPRs and two waves per SIMD, and is still
+    // faster (same box, 512^2 N = 3: 48.3 -> 42.4 us; 2048^2: 825 -> 815 us).
+    constexpr bool KEEP = MODE == MODE_STEP;
     Keep fown;
     node1<KEEP>(sm, kd, b, kd, x0, y0, tx + 2, ty + 2, psiC, &fown);
     for (int r = tid; r < RING1; r += NT) {
@@ -338,6 +340,7 @@ struct Step2D {
     const int tid = threadIdx.x;
     const int tx = tid % TX, ty = tid / TX;
     D psiC[N], psimu_d[N], dummy[N];
+    // registers kept in float arithmetic only (float64 batches untimed)
     constexpr bool KEEP = MODE == MODE_STEP && sizeof(R) == 4;
     Keep fown;
     node1<KEEP>(sm, kd, b, gd, x0, y0, tx + 2, ty + 2, psiC, &fown);
