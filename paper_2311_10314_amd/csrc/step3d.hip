@@ -199,7 +199,11 @@ __global__ __launch_bounds__(TX* TY) void k_frac3d(Coef<double> k,
 // neighbour (the 19-point stencil otherwise issues 19 loads per node and
 // field through L2). Loads, sums and their order are those of the gathered
 // form.
-constexpr int ZB = 16;  // planes per workgroup
+// Planes per workgroup: each column reloads two halo planes, but more
+// columns run at once (same box, 256^3 per step, 16 -> 8 planes: FP32 2.86 ->
+// 2.80 ms, FP16 and BF16 0.5 % faster, FP64 unchanged; 4 planes: FP32 2.78
+// ms, the others 1 % slower than at 16; 32 planes slower for all).
+constexpr int ZB = 8;
 
 template <int N, class Pop, class S, int TY>
 __global__ __launch_bounds__(TX* TY) void k_mu3d(Coef<double> k, Bufs<Pop, S> b) {
