@@ -178,3 +178,29 @@ def test_component_wise_m2g_does_not_reproduce_eq19():
     K = 0.6
     printed = K * (1 - 0.8) * (1.37 - 2.0) / 1.37
     assert abs(got - printed) > 1e-3
+
+
+def test_printed_3d_pressure_constants_hold_for_the_3d_workload():
+    """Appendix C's recipe gives the printed 3D constant of the
+    u.grad(phi rho) term only when the fourth-order rows relax at s21 (with
+    s4 != s21 the D3Q19 coefficient differs, e.g. by 2x at s21 = 1.6,
+    s4 = 1.2). In the 3D sphere workload (nu = 0.1 in both phases, d0 =
+    0.4) eq. (16) gives s21 = 1 / (2 nu / (1 - d0) + 1/2) = 1.2 at every
+    node, equal to its s4 = 1.2, so there the printed constants are the
+    recipe's."""
+    from paper_2311_10314_amd import workloads as W
+    wl = W.droplet_impact_sphere_3d(16)
+    prm = D.Params(dim=3, lattice_f=wl.lattice_f, lattice_g=wl.lattice_g,
+                   **wl.params)
+    s21, _ = D.flow_rates(prm, np.array(prm.nu).mean())
+    assert np.all(np.array(prm.nu) == prm.nu[0])
+    assert abs(s21 - prm.s_g["4"]) < 1e-12
+    lat = prm.lat_g
+    rates = {"0": prm.s_g["0"], "1": prm.s_g["1"], "21": s21, "22": 1.5,
+             "3": prm.s_g["3"], "4": prm.s_g["4"]}
+    rng = np.random.default_rng(5)
+    u = rng.normal(size=3)
+    b = rng.normal(size=3)
+    got = _pressure_recipe(lat, rates, u, b, np.zeros((3, 3)),
+                           np.zeros(3)) / (u @ b)
+    assert abs(got - prm.K * prm.Hfac * (s21 - 2.0) / s21) < 1e-12

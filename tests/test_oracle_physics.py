@@ -380,3 +380,86 @@ def test_d3q7_and_d3q15_phase_sets_agree():
     assert np.abs(res["D3Q7"][0] - res["D3Q15"][0]).max() < 0.1 * change
     assert np.abs(res["D3Q7"][1] - res["D3Q15"][1]).max() < \
         0.05 * np.abs(res["D3Q15"][1]).max()
+
+
+def _curved_cap_angle(theta, steps=1500, n=96, Rs=20.0, Rl=16.0):
+    """Droplet on a psi-embedded disk (the geometry of the 128^2 disk case,
+    scaled down): the droplet of radius Rl starts as the circle that meets
+    the disk of radius Rs at the angle theta, the wall has angle theta, and
+    after `steps` steps a circle is fitted to the C_1 = 1/2 contour away
+    from the wall. The contact angle follows from the triangle of the two
+    centres and a contact point (law of cosines):
+    cos theta = (Rs^2 + R^2 - d^2) / (2 Rs R), d the centre distance."""
+    prm = params_2d()
+    x, y = W._grid((n, n))
+    c = (n / 2, n / 2 - 10)
+    ds = W.periodic_distance((x, y), c, (n, n))
+    psi = W.psi_from_distance(ds - Rs)
+    geo = O.Geometry(prm, psi, np.full((1, n, n),
+                                       math.cos(math.radians(theta))))
+    d0 = math.sqrt(Rs * Rs + Rl * Rl
+                   - 2 * Rs * Rl * math.cos(math.radians(theta)))
+    C1 = W.droplet(W.periodic_distance((x, y), (c[0], c[1] + d0), (n, n)),
+                   Rl, prm.eps)
+    st = O.run(prm, geo, O.init_state(prm, geo, np.array([C1, 1 - C1])),
+               steps)
+    C = O.moments(prm, geo, st)[0][0]
+    far = ds > Rs + 4
+    pts = []
+    for j in range(n - 1):
+        for i in range(n - 1):
+            for dj, di in ((0, 1), (1, 0)):
+                if not (far[j, i] and far[j + dj, i + di]):
+                    continue
+                a, b = C[j, i] - 0.5, C[j + dj, i + di] - 0.5
+                if a * b <= 0 and a != b:
+                    t = a / (a - b)
+                    pts.append((i + t * di, j + t * dj))
+    p = np.array(pts)
+    A = np.c_[2 * p[:, 0], 2 * p[:, 1], np.ones(len(p))]
+    (xc, yc, cc), *_ = np.linalg.lstsq(A, (p ** 2).sum(axis=1), rcond=None)
+    R = math.sqrt(cc + xc * xc + yc * yc)
+    d = math.hypot(xc - c[0], yc - c[1])
+    cos = (Rs * Rs + R * R - d * d) / (2 * Rs * R)
+    return math.degrees(math.acos(max(-1.0, min(1.0, cos))))
+
+
+@pytest.mark.parametrize("theta", [60.0, 120.0])
+def test_contact_angle_curved_wall(theta):
+    """Young's angle on a curved psi-embedded wall (eqs. 2.9, 2.14 on a disk,
+    as in Section 4.4 for a sphere): a cap started at the wall angle keeps
+    it within 2 degrees after 1500 steps (measured 60.4 and 121.2; started
+    at 90 degrees on these walls the caps move to 87.5 and 93.9 in the same
+    time, so the wetting term, not the initial shape, holds the angle)."""
+    assert abs(_curved_cap_angle(theta) - theta) < 2.0
+
+
+def test_laplace_law_static_droplet_3d():
+    """3D pressure jump across a static droplet: P_in - P_out = 2 sigma / R
+    (Section 2.1 with the force of eq. 3.13 and the pressure of eq. 19 on
+    the D3Q19 flow set, K = w_0 / (1 - d0)), with D3Q15 phase sets at the
+    production rates. 24^3 box, R = 7, eps = 4, started from the jump and
+    averaged over steps 100-300 (acoustic oscillations of a few percent
+    remain; measured 0.974 of 2 sigma / R). Catches a wrong 3D pressure
+    prefactor c_s^2 / (1 - w_0), a 2D curvature factor and a wrong 3D
+    force."""
+    n, R, sigma = 24, 7.0, 0.01
+    shape = (n, n, n)
+    p = W.default_params(3, 2)
+    p.update(eps=4.0)
+    prm = O.Params(dim=3, lattice_f="D3Q15", lattice_g="D3Q19", **p)
+    geo = O.Geometry(prm, np.ones(shape), np.zeros((1,) + shape))
+    x, y, z = W._grid(shape)
+    C1 = W.droplet(W.periodic_distance((x, y, z), (n / 2, n / 2, n / 2),
+                                       shape), R, prm.eps)
+    st = O.init_state(prm, geo, np.array([C1, 1 - C1]), None,
+                      2 * sigma / R * C1)
+    st = O.run(prm, geo, st, 100)
+    c = n // 2
+    jumps = []
+    for _ in range(20):
+        st = O.run(prm, geo, st, 10)
+        P = O.moments(prm, geo, st)[2]
+        jumps.append(P[c - 1:c + 2, c - 1:c + 2, c - 1:c + 2].mean()
+                     - P[:2, :2, :2].mean())
+    assert abs(np.mean(jumps) * R / (2 * sigma) - 1.0) < 0.06
