@@ -165,6 +165,25 @@ int ddcc_read_moments_dev(ddcc_ctx* ctx, double* C_dev, double* u_dev,
  * Returns DDCC_E_NONFINITE if any population is NaN or Inf. */
 int ddcc_mass(ddcc_ctx* ctx, double* mass /* [nphase] */);
 
+/* ddcc_mass for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * calls no hipMalloc, hipFree or other allocating routine. The per-block
+ * partial sums live in a static device workspace of the library, one copy
+ * per GPU of 36 KiB (1024 blocks x 4 phases float64 plus 1024 flags), held
+ * until the process ends; every call on one GPU shares it, so calls that
+ * overlap on one GPU (contexts on different streams) race and must be
+ * ordered by the caller. Contexts never need more than that workspace;
+ * DDCC_E_INVAL with a message if one did.
+ * mass_dev      device float64 [nphase] out: the masses of ddcc_mass, bit for
+ *               bit (same partials, summed in the same block order)
+ * nonfinite_dev device int out (may be NULL): 1 if a population was NaN or
+ *               Inf, else 0
+ * Enqueues on the context stream and returns without synchronising; the
+ * outputs are valid once the stream has run (ddcc_sync). Errors:
+ * DDCC_E_INVAL (NULL ctx or mass_dev), DDCC_E_STATE (before init_fields),
+ * DDCC_E_HIP. */
+int ddcc_mass_noalloc(ddcc_ctx* ctx, double* mass_dev, int* nonfinite_dev);
+
 /* Number of completed steps since ddcc_init_fields. */
 int64_t ddcc_time(const ddcc_ctx* ctx);
 

@@ -526,7 +526,7 @@ int ddcc_create(const ddcc_params* p, void* stream, ddcc_ctx** out) {
   if (e == hipSuccess && p->dim == 3)
     e = hipMalloc(&c->work, (size_t)2 * p->nphase * n * sizeof(double));
   long long mb = (c->n + 255) / 256;
-  c->mass_blocks = (int)(mb > 1024 ? 1024 : mb);
+  c->mass_blocks = (int)(mb > kScratchBlocks ? kScratchBlocks : mb);
   if (e == hipSuccess)
     e = hipMalloc(&c->partial,
                   (size_t)c->mass_blocks * p->nphase * sizeof(double));
@@ -773,6 +773,31 @@ int ddcc_mass(ddcc_ctx* c, double* mass) {
   }
   for (int b = 0; b < c->mass_blocks; ++b)
     if (bad[b]) return fail(c, DDCC_E_NONFINITE, "non-finite population");
+  return DDCC_OK;
+}
+
+int ddcc_mass_noalloc(ddcc_ctx* c, double* mass_dev, int* nonfinite_dev) {
+  if (!c || !mass_dev) return fail(c, DDCC_E_INVAL, "NULL argument");
+  if (!c->fields_ok) return fail(c, DDCC_E_STATE, "init_fields first");
+  const int N = c->p.nphase;
+  void* ws = nullptr;
+  size_t cap = 0;
+  HIPCHK(c, scratch_address(c->device, &ws, &cap), "static workspace address");
+  const size_t part_bytes = (size_t)kScratchBlocks * kMaxN * sizeof(double);
+  const size_t need_part = (size_t)c->mass_blocks * N * sizeof(double);
+  const size_t need_bad = (size_t)c->mass_blocks * sizeof(int);
+  if (c->mass_blocks > kScratchBlocks || need_part > part_bytes ||
+      part_bytes + need_bad > cap)
+    return fail(c, DDCC_E_INVAL,
+                "mass check needs more than the static workspace (1024 "
+                "blocks of partial sums)");
+  double* partial = static_cast<double*>(ws);
+  int* bad = reinterpret_cast<int*>(static_cast<char*>(ws) + part_bytes);
+  hipError_t e = mass_into(c, partial, bad);
+  if (e == hipSuccess)
+    e = launch_mass_finish(partial, bad, c->mass_blocks, N, mass_dev,
+                           nonfinite_dev, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "mass kernel");
   return DDCC_OK;
 }
 

@@ -120,6 +120,21 @@ hipError_t launch_mass(const double* f0, const Pop* f, int nphase, int Q,
                        long long n, long long stride_n, double* partial,
                        int* bad, int nblocks, hipStream_t st);
 
+// Blocks of the mass kernel whose partials fit the static workspace of the
+// allocation-free mass check (the library never launches more).
+constexpr int kScratchBlocks = 1024;
+
+// Device address and size of that workspace on `device` (looked up once per
+// device, with the device made current for the lookup).
+hipError_t scratch_address(int device, void** ptr, size_t* bytes);
+
+// out[i] = sum over blocks b in order of partial[b * N + i] (i < N, float64,
+// as ddcc_mass sums them on the host); *nonfinite = OR of bad[0 .. nb) when
+// nonfinite is not NULL. One wave.
+hipError_t launch_mass_finish(const double* partial, const int* bad, int nb,
+                              int N, double* out, int* nonfinite,
+                              hipStream_t st);
+
 // *first = t if any of bad[0 .. nb) is set and *first < 0 (one wave).
 hipError_t launch_sticky(const int* bad, int nb, long long* first,
                          long long t, hipStream_t st);

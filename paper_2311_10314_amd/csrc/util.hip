@@ -1,9 +1,21 @@
 // Reductions and conversions used by the host API.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "kernels.hpp"
 
 namespace ddcc {
+
+// Workspace of the mass check that allocates nothing (ddcc_mass_noalloc):
+// the per-block partial sums [kScratchBlocks][kMaxN] float64, then the
+// per-block non-finite flags [kScratchBlocks] int. One copy per GPU, held
+// until the process ends; every call on a GPU shares it (calls that overlap
+// on one GPU race). Host code never passes this name to a kernel: it takes
+// the device address from scratch_address().
+static __device__ __align__(256) unsigned char
+    scratch[kScratchBlocks * kMaxN * sizeof(double) +
+            kScratchBlocks * sizeof(int)];
 
 namespace {
 
@@ -127,7 +139,65 @@ __global__ void k_wet_field(const double* psik, const double* ctk, int K,
   for (int i = 0; i < nm1; ++i) wet_out[i * stride + off + idx] = S(E[i]);
 }
 
+// Per-phase totals from the per-block partials, summed in block order by
+// one lane per phase (the order and arithmetic of ddcc_mass's host sum, so
+// the two agree bit for bit), and the OR of the block flags.
+__global__ __launch_bounds__(64) void k_mass_finish(const double* partial,
+                                                    const int* bad, int nb,
+                                                    int N, double* out,
+                                                    int* nonfinite) {
+  const int i = int(threadIdx.x);
+  if (i < N) {
+    double s = 0.0;
+    for (int b = 0; b < nb; ++b) s += partial[(long long)b * N + i];
+    out[i] = s;
+  }
+  if (nonfinite) {
+    int f = 0;
+    for (int b = i; b < nb; b += 64) f |= bad[b];
+    for (int off = 32; off > 0; off >>= 1) f |= __shfl_xor(f, off);
+    if (i == 0) *nonfinite = f;
+  }
+}
+
 }  // namespace
+
+hipError_t scratch_address(int device, void** ptr, size_t* bytes) {
+  // Device addresses of `scratch`, looked up once per device with that
+  // device current (each GPU holds its own copy at its own address).
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static void* addr[kMaxDevices] = {};
+  *ptr = nullptr;
+  *bytes = sizeof(scratch);
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[device]) {
+    int prev = -1;
+    hipError_t e = hipGetDevice(&prev);
+    if (e != hipSuccess) return e;
+    if (prev != device && (e = hipSetDevice(device)) != hipSuccess) return e;
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (prev != device) {
+      const hipError_t e2 = hipSetDevice(prev);
+      if (e == hipSuccess) e = e2;
+    }
+    if (e != hipSuccess) return e;
+    addr[device] = p;
+  }
+  *ptr = addr[device];
+  return hipSuccess;
+}
+
+hipError_t launch_mass_finish(const double* partial, const int* bad, int nb,
+                              int N, double* out, int* nonfinite,
+                              hipStream_t st) {
+  if (nb < 1 || N < 1 || N > kMaxN || !out) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_mass_finish, dim3(1), dim3(64), 0, st, partial, bad,
+                     nb, N, out, nonfinite);
+  return hipGetLastError();
+}
 
 template <class S>
 hipError_t launch_wet_field(const double* psik, const double* ctk, int K,

@@ -79,6 +79,7 @@ def _load():
         "ddcc_read_moments": (ctypes.c_int, [ctx, dp, dp, dp]),
         "ddcc_read_moments_dev": (ctypes.c_int, [ctx, vp, vp, vp]),
         "ddcc_mass": (ctypes.c_int, [ctx, dp]),
+        "ddcc_mass_noalloc": (ctypes.c_int, [ctx, vp, vp]),
         "ddcc_time": (ctypes.c_int64, [ctx]),
         "ddcc_save": (ctypes.c_int, [ctx, vp, P(ctypes.c_size_t)]),
         "ddcc_load": (ctypes.c_int, [ctx, vp, ctypes.c_size_t]),
@@ -136,6 +137,7 @@ ddcc_step = LIB.ddcc_step
 ddcc_read_moments = LIB.ddcc_read_moments
 ddcc_read_moments_dev = LIB.ddcc_read_moments_dev
 ddcc_mass = LIB.ddcc_mass
+ddcc_mass_noalloc = LIB.ddcc_mass_noalloc
 ddcc_time = LIB.ddcc_time
 ddcc_save = LIB.ddcc_save
 ddcc_load = LIB.ddcc_load
@@ -316,6 +318,13 @@ class Sim:
         m = np.empty(self.nphase)
         self._check(LIB.ddcc_mass(self._h, _dptr(m)))
         return m
+
+    def mass_noalloc(self, mass_dev, nonfinite_dev=None):
+        """ddcc_mass_noalloc into device tensors (float64 [nphase], int32
+        [1] or None); asynchronous on the context stream."""
+        self._check(LIB.ddcc_mass_noalloc(
+            self._h, mass_dev.data_ptr(),
+            None if nonfinite_dev is None else nonfinite_dev.data_ptr()))
 
     @property
     def time(self):
