@@ -463,3 +463,49 @@ def test_laplace_law_static_droplet_3d():
         jumps.append(P[c - 1:c + 2, c - 1:c + 2, c - 1:c + 2].mean()
                      - P[:2, :2, :2].mean())
     assert abs(np.mean(jumps) * R / (2 * sigma) - 1.0) < 0.06
+
+
+def _heavy_drop_on_wall(steps, monkeypatch=None, printed=False):
+    """A droplet of density 1 in an ambient of density 0.01 (the density
+    ratio of Section 4.1) half-way into a psi-embedded flat wall (90 deg),
+    sigma = 0.01, m0 = 0.01, 64 x 48 box. Returns max |u| after `steps`
+    steps and after half of them. printed: the volume fractions divided by
+    psi (floored at 1e-6) as printed, instead of by sum_j phi C_j."""
+    nx, ny, R, yw = 64, 48, 12.0, 8.0
+    p = W.default_params(2, 2)
+    p.update(rho=[1.0, 0.01], sigma=[[0.0, 0.01], [0.01, 0.0]], m0=0.01)
+    if printed:
+        p.update(psi_min=1e-6)
+        monkeypatch.setattr(O, "volume_fractions",
+                            lambda prm, geo, psiC: psiC / geo.psi_hat)
+    prm = O.Params(dim=2, lattice_f="D2Q9", lattice_g="D2Q9", **p)
+    x, y = W._grid((ny, nx))
+    psi = W.psi_from_distance(np.abs(W._periodic_delta(y, yw - 8.0, ny)) - 8.0)
+    geo = O.Geometry(prm, psi, np.zeros((1, ny, nx)))
+    C1 = W.droplet(np.sqrt((x - nx / 2) ** 2 + (y - yw) ** 2), R, prm.eps)
+    st = O.init_state(prm, geo, np.array([C1, 1 - C1]))
+    m0 = O.mass(st)
+    st = O.run(prm, geo, st, steps // 2)
+    u_half = np.abs(O.moments(prm, geo, st)[1]).max()
+    st = O.run(prm, geo, st, steps - steps // 2)
+    u_end = np.abs(O.moments(prm, geo, st)[1]).max()
+    return u_half, u_end, np.abs(O.mass(st) - m0) / np.abs(m0)
+
+
+def test_density_ratio_100_droplet_stays_bounded():
+    """Bounded state at the paper's density ratio 1 : 0.01 (Section 4.1):
+    the spurious currents of a heavy droplet on a wall decay (measured
+    max |u| 3.9e-5 at step 1250, 3.3e-5 at 3000) and each phase's mass is
+    conserved."""
+    u_half, u_end, drift = _heavy_drop_on_wall(1500)
+    assert np.isfinite(u_end) and u_end < 1e-4 and u_end <= u_half
+    assert drift.max() < 1e-12
+
+
+def test_printed_volume_fraction_divisor_diverges(monkeypatch):
+    """The same run with the printed divisor C_i = phi C_i / phi (psi_min =
+    1e-6) instead of sum_j phi C_j: the currents grow (6e-4 at step 1000,
+    1e-3 at 1250) and the run is non-finite by step 1750. This decides the
+    reading of the volume fractions for the oracle and the library."""
+    u_half, u_end, _ = _heavy_drop_on_wall(1500, monkeypatch, printed=True)
+    assert not (u_end < 1e-3)
