@@ -110,9 +110,10 @@ typedef struct ddcc_ctx ddcc_ctx;
 
 /* Fills *p with defaults: the lattice and rate choices of Section 4
  * (s_f = {1, 10/19, 1.2, 1.2, 1.2, 1.2}, s_g = {1, 1.2, -, -, 1.2, 1.2}),
- * d0 = 0.4, eps = 5, m0 = 0.05, rho0 = 1, psi_min = 1e-30, sigma_ij = 0.001,
- * rho = nu-independent 1, nu = 0.1, derived eta, no body force, for a 2D
- * D2Q9 N = 2 FP64 box of 64 x 64. Always returns DDCC_OK for p != NULL. */
+ * d0 = 0.4, eps = 5, m0 = 0.05, rho0 = 1, psi_min = 1e-30, sigma_ij = 0.001
+ * (i != j), rho_i = 1 and nu_i = 0.1 for every phase, eta derived by eq.
+ * (17), no body force, for a 2D D2Q9 N = 2 FP64 box of 64 x 64. Always
+ * returns DDCC_OK for p != NULL. */
 int ddcc_default_params(ddcc_params* p);
 
 /* Validates *p and allocates the device state on the current HIP device.
@@ -150,7 +151,9 @@ int ddcc_init_fields_dev(ddcc_ctx* ctx, const double* C_dev,
                          const double* u_dev, const double* P_dev);
 
 /* Advances nsteps >= 0 time steps (eqs. 3.1, 3.2), asynchronously on the
- * context stream (one fused kernel per step). */
+ * context stream: in 2D one fused kernel per step; in 3D two, one forming
+ * C_i from the pulled phase populations and one z-marching kernel for the
+ * chemical potential and the node update. */
 int ddcc_step(ddcc_ctx* ctx, int64_t nsteps);
 
 /* C_i, u and P of the current time level (moment recovery of Section 3 and

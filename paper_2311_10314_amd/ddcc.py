@@ -514,76 +514,3 @@ class Batch:
             self.close()
         except Exception:
             pass
-
-
-def unpack_state(sim, buf):
-    """Split a ddcc_save checkpoint into arrays (host side, for tests):
-    f (N, Qf, *shape), g (Qg, *shape) with g_0 stored as g_0 - rho0,
-    hist (nhist, *shape), T (nT, *shape), and the time step."""
-    hdr = np.frombuffer(buf[:8 + 8 * 4 + 16], dtype=np.uint8)
-    head = np.frombuffer(bytes(hdr[8:8 + 32]), dtype=np.int32)
-    dim, nx, ny, nz, N, lf, lg, prec = [int(v) for v in head]
-    t = int(np.frombuffer(bytes(hdr[40:48]), dtype=np.int64)[0])
-    qs = {0: 9, 1: 7, 2: 15, 3: 19}
-    Qf, Qg = qs[lf], qs[lg]
-    shape = (ny, nx) if dim == 2 else (nz, ny, nx)
-    n = nx * ny * nz
-    nhist = N * dim + dim * (dim + 1) // 2 + 1
-    nT = dim * (dim - 1) // 2
-    fdt = np.float64 if prec == FP64 else np.float32      # fields
-    pdt = {FP64: np.float64, FP32: np.float32, FP16: np.float16,
-           BF16: np.uint16}[prec]                         # populations
-    psz = np.dtype(pdt).itemsize
-    raw = bytes(buf[56:])
-
-    def pops(offset, count):
-        a = np.frombuffer(raw[offset:offset + count * psz], pdt)
-        if prec == BF16:      # bfloat16 is the high half of a float32
-            a = (a.astype(np.uint32) << 16).view(np.float32)
-        return a.astype(np.float64)
-
-    npop = N * Qf * n
-    f = pops(0, npop).reshape((N, Qf) + shape)
-    o = npop * psz
-    f[:, 0] = np.frombuffer(raw[o:o + N * n * 8], np.float64).reshape(
-        (N,) + shape)       # the rest populations live in a float64 plane
-    o += N * n * 8
-    g = pops(o, Qg * n).reshape((Qg,) + shape)
-    o += Qg * n * psz
-    data = np.frombuffer(raw[o:], dtype=fdt)
-    hist = data[:nhist * n].reshape((nhist,) + shape)
-    T = data[nhist * n:(nhist + nT) * n].reshape((nT,) + shape)
-    return dict(f=f, g=g, hist=hist, T=T, t=t, dim=dim, N=N, lf=lf, lg=lg)
-
-
-VELOCITIES = {
-    0: [(0, 0), (1, 0), (0, 1), (-1, 0), (0, -1), (1, 1), (-1, 1), (-1, -1),
-        (1, -1)],
-    1: [(0, 0, 0), (1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1),
-        (0, 0, -1)],
-    2: [(0, 0, 0), (1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1),
-        (0, 0, -1), (1, 1, 1), (1, 1, -1), (1, -1, 1), (1, -1, -1),
-        (-1, 1, 1), (-1, 1, -1), (-1, -1, 1), (-1, -1, -1)],
-    3: [(0, 0, 0), (1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1),
-        (0, 0, -1), (1, 1, 0), (1, -1, 0), (-1, 1, 0), (-1, -1, 0),
-        (1, 0, 1), (1, 0, -1), (-1, 0, 1), (-1, 0, -1), (0, 1, 1),
-        (0, 1, -1), (0, -1, 1), (0, -1, -1)],
-}
-
-
-def streamed(pops, lattice_id):
-    """The checkpoint holds populations before streaming (each step pulls
-    them from x - c_p). Returns the populations after streaming,
-    pops_p(x - c_p), for comparison with a post-streaming state."""
-    out = np.empty_like(pops)
-    for p, c in enumerate(VELOCITIES[lattice_id]):
-        v = pops[..., p, :, :] if pops.ndim == len(c) + 2 else pops[p]
-        r = v
-        for a, ca in enumerate(c):
-            if ca:
-                r = np.roll(r, ca, axis=-1 - a)
-        if pops.ndim == len(c) + 2:
-            out[..., p, :, :] = r
-        else:
-            out[p] = r
-    return out

@@ -1,8 +1,106 @@
-"""Shared helpers of the test suite (no method arithmetic here)."""
+"""Shared helpers of the test suite (no method arithmetic here): the
+layout of the library's checkpoints, the pull shift that turns its
+pre-streaming populations into post-streaming ones, and windows of a state
+for the oracle."""
 import numpy as np
 
 import oracle
 from paper_2311_10314_amd import workloads as W
+
+FP64, FP32, FP16, BF16 = 0, 1, 2, 3
+
+# Velocity order of each lattice id (DDCC_D2Q9 = 0, D3Q7 = 1, D3Q15 = 2,
+# D3Q19 = 3): part of the checkpoint layout, the same order as the oracle's.
+VELOCITIES = {
+    0: [(0, 0), (1, 0), (0, 1), (-1, 0), (0, -1), (1, 1), (-1, 1), (-1, -1),
+        (1, -1)],
+    1: [(0, 0, 0), (1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1),
+        (0, 0, -1)],
+    2: [(0, 0, 0), (1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1),
+        (0, 0, -1), (1, 1, 1), (1, 1, -1), (1, -1, 1), (1, -1, -1),
+        (-1, 1, 1), (-1, 1, -1), (-1, -1, 1), (-1, -1, -1)],
+    3: [(0, 0, 0), (1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1),
+        (0, 0, -1), (1, 1, 0), (1, -1, 0), (-1, 1, 0), (-1, -1, 0),
+        (1, 0, 1), (1, 0, -1), (-1, 0, 1), (-1, 0, -1), (0, 1, 1),
+        (0, 1, -1), (0, -1, 1), (0, -1, -1)],
+}
+
+
+def unpack_state(sim, buf, lazy=False):
+    """Split a ddcc_save checkpoint into arrays: f (N, Qf, *shape) with the
+    float64 rest populations in plane 0, g (Qg, *shape) with g_0 stored as
+    g_0 - rho0, hist (nhist, *shape), T (nT, *shape), and the time step.
+    lazy: f, g, hist and T are views of the buffer in the stored types
+    (f without its rest plane, which is then in "f0"), to be converted
+    piecewise with s["pops"](a) (float64 populations) and np.float64."""
+    hdr = np.frombuffer(buf[:8 + 8 * 4 + 16], dtype=np.uint8)
+    head = np.frombuffer(bytes(hdr[8:8 + 32]), dtype=np.int32)
+    dim, nx, ny, nz, N, lf, lg, prec = [int(v) for v in head]
+    t = int(np.frombuffer(bytes(hdr[40:48]), dtype=np.int64)[0])
+    qs = {0: 9, 1: 7, 2: 15, 3: 19}
+    Qf, Qg = qs[lf], qs[lg]
+    shape = (ny, nx) if dim == 2 else (nz, ny, nx)
+    n = nx * ny * nz
+    nhist = N * dim + dim * (dim + 1) // 2 + 1
+    nT = dim * (dim - 1) // 2
+    fdt = np.float64 if prec == FP64 else np.float32      # fields
+    pdt = {FP64: np.float64, FP32: np.float32, FP16: np.float16,
+           BF16: np.uint16}[prec]                         # populations
+    psz = np.dtype(pdt).itemsize
+    raw = memoryview(buf)[56:]
+    # DDCCSAV2 kept an unused plane 0 in each phase set's moving block;
+    # DDCCSAV3 stores only the moving planes p >= 1
+    skip = bytes(hdr[:8]) == b"DDCCSAV2"
+
+    def conv(a):
+        a = np.asarray(a)
+        if prec == BF16:      # bfloat16 is the high half of a float32
+            a = (a.astype(np.uint32) << 16).view(np.float32)
+        return a.astype(np.float64)
+
+    if skip:
+        fview = np.frombuffer(raw, pdt, count=N * Qf * n).reshape(
+            (N, Qf) + shape)[:, 1:]
+        o = N * Qf * n * psz
+    else:
+        fview = np.frombuffer(raw, pdt, count=N * (Qf - 1) * n).reshape(
+            (N, Qf - 1) + shape)
+        o = N * (Qf - 1) * n * psz
+    f0 = np.frombuffer(raw[o:o + N * n * 8], np.float64).reshape((N,) + shape)
+    o += N * n * 8
+    g = np.frombuffer(raw[o:o + Qg * n * psz], pdt).reshape((Qg,) + shape)
+    o += Qg * n * psz
+    data = np.frombuffer(raw[o:], dtype=fdt)
+    hist = data[:nhist * n].reshape((nhist,) + shape)
+    T = data[nhist * n:(nhist + nT) * n].reshape((nT,) + shape)
+    out = dict(g=g, hist=hist, T=T, t=t, dim=dim, N=N, lf=lf, lg=lg,
+               pops=conv)
+    if lazy:
+        out.update(fmov=fview, f0=f0)
+        return out
+    f = np.empty((N, Qf) + shape)
+    f[:, 0] = f0
+    f[:, 1:] = conv(fview)
+    out.update(f=f, g=conv(g), hist=np.asarray(hist), T=np.asarray(T))
+    return out
+
+
+def streamed(pops, lattice_id):
+    """The checkpoint holds populations before streaming (each step pulls
+    them from x - c_p). Returns the populations after streaming,
+    pops_p(x - c_p), for comparison with a post-streaming state."""
+    out = np.empty_like(pops)
+    for p, c in enumerate(VELOCITIES[lattice_id]):
+        v = pops[..., p, :, :] if pops.ndim == len(c) + 2 else pops[p]
+        r = v
+        for a, ca in enumerate(c):
+            if ca:
+                r = np.roll(r, ca, axis=-1 - a)
+        if pops.ndim == len(c) + 2:
+            out[..., p, :, :] = r
+        else:
+            out[p] = r
+    return out
 
 
 def rel_linf(a, b):
@@ -34,7 +132,6 @@ def gpu_state_to_oracle(wl, sim):
     """Oracle State built from a library checkpoint (populations after
     streaming, g_0 with rho0 added back, history unpacked)."""
     from oracle.dd_cclb import State
-    from paper_2311_10314_amd.ddcc import streamed, unpack_state
     s = unpack_state(sim, sim.save())
     N, d = s["N"], s["dim"]
     f = np.stack([streamed(np.asarray(s["f"][i], np.float64), s["lf"])
@@ -65,17 +162,25 @@ def window_state(wl, s, center, hw):
     (array indices, periodic), built from an unpack_state dict s of a
     library checkpoint. The window's own periodic wrap is wrong only near
     its edge: a node's next state depends on the state within 4 nodes, so
-    outputs within hw - 4 of the centre are those of the full box."""
+    outputs within hw - 4 of the centre are those of the full box. s may
+    be lazy (unpack_state(..., lazy=True)): only the window is converted."""
     from oracle.dd_cclb import State
-    from paper_2311_10314_amd.ddcc import streamed
     N, d = s["N"], s["dim"]
     shape = wl.shape
     pad = [(np.arange(-hw - 1, hw + 2) + c) % n for c, n in zip(center, shape)]
     sub = lambda a: a[(Ellipsis,) + np.ix_(*pad)]
     crop = (Ellipsis,) + (slice(1, -1),) * d
-    f = np.stack([streamed(np.asarray(sub(s["f"][i]), np.float64), s["lf"])
-                  for i in range(N)])[crop]
-    g = streamed(np.asarray(sub(s["g"]), np.float64), s["lg"])[crop]
+    if "f" in s:
+        fw = [np.asarray(sub(s["f"][i]), np.float64) for i in range(N)]
+    else:
+        fw = []
+        for i in range(N):
+            a = np.empty((s["fmov"].shape[1] + 1,) + tuple(len(q) for q in pad))
+            a[0] = sub(s["f0"][i])
+            a[1:] = s["pops"](sub(s["fmov"][i]))
+            fw.append(a)
+    f = np.stack([streamed(a, s["lf"]) for a in fw])[crop]
+    g = streamed(s["pops"](sub(s["g"])), s["lg"])[crop]
     g[0] += wl.params["rho0"]
     h = np.asarray(sub(s["hist"]), np.float64)[crop]
     wshape = h.shape[1:]

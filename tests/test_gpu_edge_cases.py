@@ -78,7 +78,8 @@ def test_absent_phase_stays_zero(precision, tol):
 
 
 def test_zero_steps():
-    from paper_2311_10314_amd.ddcc import Sim, unpack_state
+    from paper_2311_10314_amd.ddcc import Sim
+    from tests.helpers import unpack_state
     wl = W.random_small(2, 2, (20, 70), seed=1)
     sim = Sim.from_workload(wl, "fp64")
     sim.step(3)

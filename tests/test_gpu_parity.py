@@ -46,7 +46,7 @@ def test_init_and_moments_fp64(k):
 @pytest.mark.parametrize("k", range(4))
 def test_one_step_populations_fp64(k):
     """After one step every population of every set matches."""
-    from paper_2311_10314_amd.ddcc import streamed, unpack_state
+    from tests.helpers import streamed, unpack_state
     wl = small_cases()[k]
     print("case", wl.name, wl.shape, flush=True)
     o = oracle_run(wl, 1)
