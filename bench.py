@@ -1,23 +1,24 @@
-"""Throughput of the fused DD-CCLB step on one MI355X.
+"""Throughput of the DD-CCLB step on one MI355X.
 
-python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 512] [--skip-cpu]
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--skip-cpu] ...
 
-Workload: the 2D porous medium of the paper's setting (512 x 512 periodic
-box, 40 seeded disks with radii U[10, 30], three vertical phase bands,
-per-obstacle contact angles U[45, 135] deg, densities 1:10:100, body force
-density 1e-6), N = 3 phase sets + 1 flow set on D2Q9. One "step" is one
-time step of the whole scheme (one fused kernel launch). Both FP32 and FP64
-are timed; the JSON `value` is the FP32 figure and `fp64` holds the other.
-The 3D leg (`sphere3d`: a droplet impacting a sphere, D3Q15 phase sets and a
-D3Q19 flow set, N = 2, n^3 box) is timed in FP32, FP64 and the two 16-bit
-population storages, each with its error against the FP64 oracle on the
-same case at 32^3.
+Headline workload: the 3D droplet impacting a sphere, 256^3 periodic box
+(sphere R = 60, droplet R = 40 moving at 0.02 towards it, density ratio 10,
+90 deg walls), N = 2 phase sets on D3Q15 and a D3Q19 flow set, FP32 storage
+and arithmetic: the largest single-GPU configuration of the paper's
+setting. One "step" is one time step of the whole scheme (one kernel
+launch, k_step3d). The JSON `value` is its node-MLUPS; `roofline` prices
+the kernel against the 8 TB/s HBM peak with the algorithmic bytes of one
+node update (populations read and written once, history read and written
+once, psi and the wetting weight read once: 528 B at N = 2 in FP32, 544 B
+counting the float64 rest planes the library keeps) over the average
+launch duration from HIP events on the library's stream.
 
-MLUPS counts lattice-node updates per second, each update covering all N + 1
-distribution sets. `roofline.achieved` is the algorithmic HBM bytes of one
-node update (populations read + written once, history read + written once,
-static fields read once) times the nodes of one launch, divided by the
-average launch duration measured with HIP events on the library's stream.
+Other legs in the same line: the 3D box in FP64 and with 16-bit population
+storage, the 2D porous box (512 x 512, N = 3; it fits the 256 MB
+memory-side cache, so its rate is not an HBM roofline figure), the batch of
+256 independent 2D boxes, and the adjoint sweep. Every leg carries its
+error against the FP64 oracle and its mass drift.
 """
 import argparse
 import json
@@ -32,40 +33,62 @@ METRIC = ("MLUPS (all distribution sets) and % of HBM roofline, "
           "FP32 vs FP64 at stated error")
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.json")
-KERNEL_SOURCES = ["paper_2311_10314_amd/csrc/step2d.hip",
-                  "paper_2311_10314_amd/csrc/collide.hpp",
-                  "paper_2311_10314_amd/csrc/common.hpp",
-                  "paper_2311_10314_amd/csrc/lattice.hpp",
-                  "paper_2311_10314_amd/csrc/coef.hpp"]
-
-
+KERNEL_SOURCES = {
+    "2d": ["paper_2311_10314_amd/csrc/step2d.hip",
+           "paper_2311_10314_amd/csrc/collide.hpp",
+           "paper_2311_10314_amd/csrc/common.hpp",
+           "paper_2311_10314_amd/csrc/lattice.hpp",
+           "paper_2311_10314_amd/csrc/coef.hpp"],
+    "3d": ["paper_2311_10314_amd/csrc/step3d.hip",
+           "paper_2311_10314_amd/csrc/collide.hpp",
+           "paper_2311_10314_amd/csrc/common.hpp",
+           "paper_2311_10314_amd/csrc/lattice.hpp",
+           "paper_2311_10314_amd/csrc/coef.hpp"],
+}
+# element bytes (populations, fields) per precision
 PREC_BYTES = {"fp64": (8, 8), "fp32": (4, 4), "fp16": (2, 4), "bf16": (2, 4)}
+# the step kernels' template arguments as rocprofv3 prints them
+KERNEL_TAGS = {
+    ("3d", "fp32"): "k_step3d<2, ddcc::D3Q15, ddcc::D3Q19, float, float, float, 0, 4>",
+    ("3d", "fp64"): "k_step3d<2, ddcc::D3Q15, ddcc::D3Q19, double, double, double, 0, 4>",
+    ("3d", "fp16"): "k_step3d<2, ddcc::D3Q15, ddcc::D3Q19, _Float16, float, float, 0, 4>",
+    ("3d", "bf16"): "k_step3d<2, ddcc::D3Q15, ddcc::D3Q19, __bf16, float, float, 0, 4>",
+    ("2d", "fp32"): "k_step2d<3, float, float, float, 0, 8>",
+    ("2d", "fp64"): "k_step2d<3, double, double, double, 0, 4>",
+}
+HEAD_N = 256          # the 3D box of the headline
+REDUCED_N = 48        # the same generator at 48^3 for the oracle legs
 
 
-def algorithmic_bytes_per_node(N, dim, Qf, Qg, precision):
-    """Populations (N Qf + Qg) read and written once (the N rest populations
-    of the phase sets are float64 in every precision, the moving ones and the
-    flow set in the population storage type), history
-    (N d + d(d+1)/2 + 1 in place, d(d-1)/2 double-buffered) read and written
-    once, psi and N-1 wetting cosines read once (field storage type)."""
+def algorithmic_bytes_per_node(N, dim, Qf, Qg, precision, rest64=False):
+    """Bytes one node update must move: every population (N Qf + Qg) read
+    and written once in the population storage type, the history (N d
+    values phi C_i u, d(d+1)/2 of the symmetric flux tensor, P: in place)
+    and the antisymmetric tensor T (d(d-1)/2, double-buffered) read and
+    written once, psi and the N-1 wetting weights read once, in the field
+    type. rest64: the N rest populations of the phase sets counted as the
+    float64 the library keeps them in (so that storage rounding cannot
+    change a phase's mass)."""
     pesz, fesz = PREC_BYTES[precision]
-    pops = (N * (Qf - 1) + Qg) * 2 * pesz + N * 2 * 8
+    pops = (N * Qf + Qg) * 2 * pesz
+    if rest64:
+        pops += N * 2 * (8 - pesz)
     hist = (N * dim + dim * (dim + 1) // 2 + 1) * 2
     tens = (dim * (dim - 1) // 2) * 2
     static = 1 + (N - 1)
     return pops + (hist + tens + static) * fesz
 
 
-def kernel_source_hash():
+def kernel_source_hash(kind):
     import hashlib
     h = hashlib.sha256()
-    for rel in KERNEL_SOURCES:
+    for rel in KERNEL_SOURCES[kind]:
         with open(os.path.join(ROOT, rel), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic(precision):
+def measured_traffic(kind, precision):
     """HBM bytes per launch from the committed rocprofv3 counter runs, if
     they were taken on the current kernel source; else None."""
     try:
@@ -73,59 +96,240 @@ def measured_traffic(precision):
             t = json.load(fh)
     except (OSError, ValueError):
         return None
-    e = t.get(precision)
-    if not e or e.get("kernel_hash") != kernel_source_hash():
+    e = t.get("%s_%s" % (kind, precision))
+    if not e or e.get("kernel_hash") != kernel_source_hash(kind):
         return None
     return e.get("bytes_per_launch")
 
 
-def make_workload(n):
+def cpu_info():
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count(),
+            "affinity_cpus": len(os.sched_getaffinity(0))}
+
+
+def rel_linf(a, b):
+    import numpy as np
+    scale = float(np.abs(b).max())
+    return float(np.abs(a - b).max() / (scale if scale > 0 else 1.0))
+
+
+def field_errors(got, ref, psi):
+    """Relative L-inf of every C_i, of u and of P where psi >= 1e-2 (P =
+    phi P / phi is round-off over a vanishing psi inside solids), and of
+    phi P everywhere, against reference fields."""
+    import numpy as np
+    C, u, P = got
+    Co, uo, Po = ref
+    psi = np.asarray(psi)
+    fl = psi >= 1e-2
+    return {"rel_linf_C": max(rel_linf(C[i], Co[i]) for i in range(len(Co))),
+            "rel_linf_u": rel_linf(u, uo),
+            "rel_linf_P": rel_linf(P[fl], Po[fl]),
+            "rel_linf_psiP": rel_linf(psi * P, psi * Po)}
+
+
+def time_gpu(wl, precision, steps, warmup, torch, tile=0):
+    from paper_2311_10314_amd.ddcc import Sim
+    stream = torch.cuda.Stream()
+    sim = Sim.from_workload(wl, precision, stream=stream.cuda_stream)
+    if tile:
+        sim.set_tile(0, tile)
+    m0 = sim.mass()
+    sim.step(warmup)
+    sim.sync()
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record(stream)
+    sim.step(steps)
+    t1.record(stream)
+    t1.synchronize()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1)
+    try:
+        m1 = sim.mass()
+        drift = float(max(abs(a - b) / abs(b) for a, b in zip(m1, m0)))
+    except Exception as e:  # a non-finite state is reported, not hidden
+        print("mass check failed: %s" % e, file=sys.stderr, flush=True)
+        drift = None
+    return sim, ms / steps, drift
+
+
+
+def roofline(kind, precision, nodes, ms, N, dim, Qf, Qg, torch):
+    """Roofline object of one step kernel: algorithmic bytes of a launch
+    over its average duration, the bytes with the float64 rest planes, the
+    counter traffic (if taken on the current source) and the same-session
+    copy rate of the same bytes."""
+    bpn = algorithmic_bytes_per_node(N, dim, Qf, Qg, precision)
+    bpn64 = algorithmic_bytes_per_node(N, dim, Qf, Qg, precision, True)
+    per_launch = bpn * nodes
+    achieved = per_launch / (ms * 1e-3) / 1e9
+    copy = copy_rate(torch, bpn64 * nodes)
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+            "traffic": measured_traffic(kind, precision),
+            "kernel": KERNEL_TAGS.get((kind, precision)),
+            "bytes_per_node": bpn,
+            "algorithmic_bytes_per_launch": per_launch,
+            "bytes_per_node_with_float64_rest": bpn64,
+            "achieved_with_float64_rest": bpn64 * nodes / (ms * 1e-3) / 1e9,
+            "copy_GBs": copy, "frac_of_copy": achieved / copy}
+
+
+BATCH_ERR_STEPS = 20
+
+
+def batch_check_instances(count):
+    """Instances of the batch compared with the oracle: the three smallest
+    and the largest."""
     from paper_2311_10314_amd import workloads as W
-    return W.porous_bands_2d(n=n)
+    wls = W.batched_instances(count)
+    order = sorted(range(count), key=lambda i: wls[i].nodes)
+    return [(i, wls[i]) for i in order[:3] + order[-1:]]
 
 
-def sphere_leg(n, steps, warmup, torch, precisions):
-    """3D leg: the sphere / impacting-droplet box (D3Q15 phase sets, D3Q19
-    flow set, N = 2) at n^3, with each precision's error against the FP64
-    oracle after 40 steps of the same case at 32^3."""
+def oracle_leg(wl_small, steps, wl2d, steps2d, batch_count=0, threads=1):
+    """The cpu_baseline leg: the FP64 oracle, untuned, on one pinned core,
+    on a bounded sample of the headline workload (the same generator on a
+    reduced box, the same work per node update), timed; its results are
+    also the reference of the error columns (reduced 3D box after `steps`
+    steps, 2D porous box after `steps2d` steps)."""
+    import warnings
+
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    import oracle
+    warnings.simplefilter("ignore")
+    keep = os.sched_getaffinity(0)
+    core = min(keep)
+    try:
+        os.sched_setaffinity(0, {core})
+        with threadpool_limits(limits=threads):
+            prm, geo, st = oracle.from_workload(wl_small)
+            m0 = oracle.mass(st)
+            t = time.perf_counter()
+            st = oracle.run(prm, geo, st, steps)
+            dt = time.perf_counter() - t
+            ref3 = oracle.moments(prm, geo, st)
+            drift3 = float(np.max(np.abs(oracle.mass(st) - m0) / np.abs(m0)))
+            prm2, geo2, st2 = oracle.from_workload(wl2d)
+            st2 = oracle.run(prm2, geo2, st2, steps2d)
+            ref2 = oracle.moments(prm2, geo2, st2)
+            refb = []
+            if batch_count:
+                for i, wb in batch_check_instances(batch_count):
+                    pb, gb, sb = oracle.from_workload(wb)
+                    sb = oracle.run(pb, gb, sb, BATCH_ERR_STEPS)
+                    refb.append((i, wb, oracle.moments(pb, gb, sb)))
+    finally:
+        os.sched_setaffinity(0, keep)
+    base = {"value": wl_small.nodes * steps / dt / 1e6, "unit": "MLUPS",
+            "cores": threads, "kind": "oracle",
+            "sample": "%d steps of the %s box (%dx%dx%d, the headline's "
+                      "generator with sizes scaled by %d/%d; same work per "
+                      "node update), numpy float64, %d thread pinned to "
+                      "core %d, %.1f s" % (
+                          steps, wl_small.name, *wl_small.shape,
+                          wl_small.shape[0], HEAD_N, threads, core, dt)}
+    base.update(cpu_info())
+    return base, {"sphere": ref3, "sphere_drift": drift3, "porous": ref2,
+                  "batch": refb}
+
+
+def sampled_full_size_error(wl, sim, count, hw=5, seed=256):
+    """One more step of the full-size state against one oracle step on
+    periodic windows around `count` sampled nodes (random, the wall layer,
+    the droplet interface): a node's next state depends on the state
+    within 4 nodes, so each window's centre is exact. Worst population
+    error relative to the largest population at the centres."""
+    import numpy as np
+
+    import oracle
+    from tests.helpers import unpack_state, window, window_state
+    rng = np.random.default_rng(seed)
+    shape = wl.shape
+    pts = [tuple(int(rng.integers(0, n)) for n in shape)
+           for _ in range(count // 2)]
+    psi = np.asarray(wl.psi)
+    C = np.asarray(wl.C0[0])
+    for mask in ((psi > 0.2) & (psi < 0.8),
+                 (C > 0.2) & (C < 0.8) & (psi > 0.9)):
+        idx = np.argwhere(mask)
+        pick = rng.choice(len(idx), size=min(count // 4, len(idx)),
+                          replace=False)
+        pts += [tuple(int(v) for v in idx[k]) for k in pick]
+    s0 = unpack_state(sim, sim.save(), lazy=True)
+    sim.step(1)
+    s1 = unpack_state(sim, sim.save(), lazy=True)
+    prm = oracle.Params(dim=wl.dim, lattice_f=wl.lattice_f,
+                        lattice_g=wl.lattice_g, **wl.params)
+    worst = 0.0
+    c = (hw,) * len(shape)
+    for center in pts:
+        geo = oracle.Geometry(prm, window(psi, center, hw),
+                              window(np.asarray(wl.cos_theta_iN), center,
+                                     hw))
+        st1 = oracle.step(prm, geo, window_state(wl, s0, center, hw))
+        got = window_state(wl, s1, center, hw)
+        for a, b in ((got.f, st1.f), (got.g, st1.g)):
+            ref = b[(Ellipsis,) + c]
+            worst = max(worst, float(np.abs(a[(Ellipsis,) + c] - ref).max()
+                                     / np.abs(ref).max()))
+    return {"rel_linf_populations": worst, "nodes": len(pts),
+            "case": "one step after %d, windows of %d^%d" % (
+                s0["t"], 2 * hw + 1, len(shape))}
+
+
+def batch_errors(refs, count, torch):
+    """The whole batch (FP32, graph step loop) for BATCH_ERR_STEPS steps,
+    the checked instances against the oracle."""
     import numpy as np
 
     from paper_2311_10314_amd import workloads as W
-    from paper_2311_10314_amd.ddcc import Sim
-    wl = W.droplet_impact_sphere_3d(n=n)
-    small = W.droplet_impact_sphere_3d(n=32)
-    ref = None
+    from paper_2311_10314_amd.ddcc import Batch
+    b = Batch.from_workloads(W.batched_instances(count), "fp32")
+    b.set_graph(10)
+    m0 = {i: b.mass(i) for i, _, _ in refs}
+    b.step(BATCH_ERR_STEPS)
     out = {}
-    for prec in precisions:
-        sim, ms, drift = time_gpu(wl, prec, steps, warmup, torch)
-        sim.close()
-        bpn = algorithmic_bytes_per_node(2, 3, 15, 19, prec)
-        achieved = bpn * wl.nodes / (ms * 1e-3) / 1e9
-        if ref is None:
-            import oracle
-            prm, geo, st = oracle.from_workload(small)
-            st = oracle.run(prm, geo, st, 40)
-            ref = oracle.moments(prm, geo, st)
-        s2 = Sim.from_workload(small, prec)
-        s2.step(40)
-        C, u, _ = s2.read_moments()
-        s2.close()
-        Co, uo, _ = ref
-        err = {"rel_linf_C": max(float(np.abs(C[i] - Co[i]).max() /
-                                       np.abs(Co[i]).max())
-                                 for i in range(len(Co))),
-               "rel_linf_u": float(np.abs(u - uo).max() / np.abs(uo).max()),
-               "case": "32^3, 40 steps"}
-        out[prec] = {"value": wl.nodes / (ms * 1e-3) / 1e6,
-                     "unit": "MLUPS", "ms_per_step": ms, "mass_drift": drift,
-                     "bytes_per_node": bpn, "achieved_GBs": achieved,
-                     "frac": achieved / HBM_PEAK_GBS, "steps": steps,
-                     "error_vs_oracle": err}
-        print("  sphere3d %d^3 %s: %.4f ms/step, %.0f MLUPS, %.0f GB/s%s" % (
-            n, prec, ms, out[prec]["value"], achieved,
-            ", C %.1e u %.1e" % (err["rel_linf_C"], err["rel_linf_u"])),
-            file=sys.stderr, flush=True)
+    for i, wb, ref in refs:
+        e = field_errors(b.read_moments(i), ref, wb.psi)
+        e["mass_drift"] = float(np.max(np.abs(b.mass(i) - m0[i])
+                                       / np.abs(m0[i])))
+        e["shape"] = list(wb.shape)
+        out["instance_%d" % i] = e
+    b.close()
+    out["steps"] = BATCH_ERR_STEPS
     return out
+
+
+def gpu_errors(wl, precision, steps, ref, torch):
+    """The library on a workload for `steps` steps against oracle fields,
+    with its mass drift."""
+    import numpy as np
+
+    from paper_2311_10314_amd.ddcc import Sim
+    sim = Sim.from_workload(wl, precision)
+    m0 = sim.mass()
+    sim.step(steps)
+    got = sim.read_moments()
+    drift = float(np.max(np.abs(sim.mass() - m0) / np.abs(m0)))
+    sim.close()
+    e = field_errors(got, ref, wl.psi)
+    e.update({"mass_drift": drift, "steps": steps,
+              "case": "%s %s" % (wl.name, "x".join(map(str, wl.shape)))})
+    return e
 
 
 def batched_leg(count, steps, torch, graph_steps=50):
@@ -169,7 +373,6 @@ def batched_leg(count, steps, torch, graph_steps=50):
                                        achieved, ty), file=sys.stderr,
           flush=True)
     return out
-
 
 def adjoint_leg(n, steps, interval, torch):
     """Adjoint sweep on the wavy channel (256 x 256, N = 2, per-node angle
@@ -235,7 +438,6 @@ def adjoint_leg(n, steps, interval, torch):
         p[3].close()
     return out
 
-
 def copy_calibration(torch, mib=1024):
     """A plain device copy of known size, for scaling the HBM byte counters
     (FETCH_SIZE / WRITE_SIZE) read on the step kernel."""
@@ -247,7 +449,6 @@ def copy_calibration(torch, mib=1024):
     torch.cuda.synchronize()
     print("copy calibration: 3 copies of %d MiB" % mib, file=sys.stderr,
           flush=True)
-
 
 def copy_rate(torch, nbytes, reps=None):
     """Streaming reference measured in the same session: GB/s of the
@@ -275,7 +476,6 @@ def copy_rate(torch, nbytes, reps=None):
     del a, b
     torch.cuda.empty_cache()
     return 2 * half * 4 / (ms * 1e-3) / 1e9
-
 
 def sweep(torch, out_path=None):
     """Roofline sweep of the 2D step over grid sizes, phase counts and
@@ -324,57 +524,57 @@ def sweep(torch, out_path=None):
     return rows
 
 
-STEP_KERNEL = {"fp32": "float, float, float", "fp64": "double, double, double"}
-
-
-def _counter_means(csv_path, counter, precision, nphase):
-    """Mean counter value (KiB per dispatch) of the step kernel and of the
-    1 GiB calibration copy (the largest buffer-copy dispatch) in one
-    rocprofv3 counter run."""
+def _counter_means(csv_path, counter, tag):
+    """Mean counter value (KiB per dispatch) of the kernel whose name
+    contains `tag`, and of the 1 GiB calibration copy (the largest
+    buffer-copy dispatch) in one rocprofv3 counter run."""
     import csv
-    step, copy = [], []
-    tag = "k_step2d<%d, %s, 0, " % (nphase, STEP_KERNEL[precision])
     with open(csv_path) as fh:
         rows = [r for r in csv.DictReader(fh) if r["Counter_Name"] == counter]
-    for r in rows:
-        if tag in r["Kernel_Name"]:
-            step.append(float(r["Counter_Value"]))
+    step = [float(r["Counter_Value"]) for r in rows if tag in r["Kernel_Name"]]
     # the 1 GiB calibration copies: the largest copy dispatches of the run
     # (the runtime's copy kernel keeps one grid size for all large copies,
     # so they are told apart by their counter values)
     copies = [float(r["Counter_Value"]) for r in rows
               if "copyBuffer" in r["Kernel_Name"]]
+    copy = []
     if copies:
         top = max(copies)
         copy = [v for v in copies if v >= 0.9 * top]
     if not step or not copy or max(copy) < 1.0e5:
-        raise SystemExit("%s: no %s dispatches of the step kernel or of the "
-                         "1 GiB copy (run with --copy-calibration)"
-                         % (csv_path, counter))
+        raise SystemExit("%s: no %s dispatches of %s or of the 1 GiB copy "
+                         "(run with --copy-calibration)"
+                         % (csv_path, counter, tag))
     return sum(step) / len(step), sum(copy) / len(copy), len(step)
 
 
-def traffic_summary(fetch_dir, write_dir, precision, n):
-    """Scale the FETCH_SIZE and WRITE_SIZE counters of the step kernel by
-    what they read for a 1 GiB device copy in the same run, and record the
-    HBM bytes per launch in profiles/hbm_traffic.json under the hash of the
+def traffic_summary(fetch_dir, write_dir, kind, precision):
+    """Scale the FETCH_SIZE and WRITE_SIZE counters of a step kernel by what
+    they read for a 1 GiB device copy in the same run, and record the HBM
+    bytes per launch in profiles/hbm_traffic.json under the hash of the
     kernel sources (bench.py reports them only while the hash matches)."""
-    wl = make_workload(n)
-    N = wl.nphase
+    from paper_2311_10314_amd import workloads as W
+    if kind == "3d":
+        wl = W.droplet_impact_sphere_3d(n=HEAD_N)
+        geom = (2, 3, 15, 19)
+    else:
+        wl = W.porous_bands_2d(n=512)
+        geom = (3, 2, 9, 9)
+    tag = KERNEL_TAGS[(kind, precision)].split("<")[0] + "<" + \
+        KERNEL_TAGS[(kind, precision)].split("<", 1)[1]
     f_step, f_copy, nd = _counter_means(
         os.path.join(fetch_dir, "run_counter_collection.csv"), "FETCH_SIZE",
-        precision, N)
+        tag)
     w_step, w_copy, _ = _counter_means(
         os.path.join(write_dir, "run_counter_collection.csv"), "WRITE_SIZE",
-        precision, N)
+        tag)
     gib_kib = 1024.0 * 1024.0
     ff, wf = gib_kib / f_copy, gib_kib / w_copy
     per_launch = (f_step * ff + w_step * wf) * 1024.0
-    ty = 4 if precision == "fp64" else 8   # the library's default tiles
-    entry = {"kernel": "k_step2d<%d, %s, 0, %d>" % (N, STEP_KERNEL[precision],
-                                                     ty),
-             "workload": "porous_bands_2d %dx%d N=%d" % (n, n, N),
-             "kernel_hash": kernel_source_hash(),
+    alg = algorithmic_bytes_per_node(*geom, precision) * wl.nodes
+    entry = {"kernel": KERNEL_TAGS[(kind, precision)],
+             "workload": "%s %s" % (wl.name, "x".join(map(str, wl.shape))),
+             "kernel_hash": kernel_source_hash(kind),
              "dispatches": nd,
              "fetch_kib_per_dispatch": f_step,
              "write_kib_per_dispatch": w_step,
@@ -384,102 +584,38 @@ def traffic_summary(fetch_dir, write_dir, precision, n):
              "read_bytes_per_launch": f_step * ff * 1024.0,
              "write_bytes_per_launch": w_step * wf * 1024.0,
              "bytes_per_launch": per_launch,
-             "algorithmic_bytes_per_launch":
-                 algorithmic_bytes_per_node(N, 2, 9, 9, precision) * wl.nodes}
+             "algorithmic_bytes_per_launch": alg,
+             "ratio_to_algorithmic": per_launch / alg}
     try:
         with open(TRAFFIC_FILE) as fh:
             t = json.load(fh)
     except (OSError, ValueError):
         t = {}
-    t[precision] = entry
+    t["%s_%s" % (kind, precision)] = entry
     with open(TRAFFIC_FILE, "w") as fh:
-        json.dump(t, fh, indent=1)
+        json.dump(t, fh, indent=1, sort_keys=True)
         fh.write("\n")
     print(json.dumps(entry, indent=1))
-
-
-def time_gpu(wl, precision, steps, warmup, torch, tile=0):
-    from paper_2311_10314_amd.ddcc import Sim
-    stream = torch.cuda.Stream()
-    sim = Sim.from_workload(wl, precision, stream=stream.cuda_stream)
-    if tile:
-        sim.set_tile(0, tile)
-    m0 = sim.mass()
-    sim.step(warmup)
-    sim.sync()
-    torch.cuda.synchronize()
-    t0 = torch.cuda.Event(enable_timing=True)
-    t1 = torch.cuda.Event(enable_timing=True)
-    t0.record(stream)
-    sim.step(steps)
-    t1.record(stream)
-    t1.synchronize()
-    torch.cuda.synchronize()
-    ms = t0.elapsed_time(t1)
-    try:
-        m1 = sim.mass()
-        drift = float(max(abs(a - b) / abs(b) for a, b in zip(m1, m0)))
-    except Exception as e:  # a non-finite state is reported, not hidden
-        print("mass check failed: %s" % e, file=sys.stderr, flush=True)
-        drift = None
-    return sim, ms / steps, drift
-
-
-def error_vs_oracle(wl, steps):
-    """Relative L-inf of C_i and u after `steps` steps, GPU vs oracle."""
-    import numpy as np
-
-    import oracle
-    from paper_2311_10314_amd.ddcc import Sim
-    prm, geo, st = oracle.from_workload(wl)
-    st = oracle.run(prm, geo, st, steps)
-    Co, uo, _ = oracle.moments(prm, geo, st)
-    out = {}
-    for prec in ("fp64", "fp32"):
-        sim = Sim.from_workload(wl, prec)
-        sim.step(steps)
-        C, u, _ = sim.read_moments()
-        eC = max(float(np.abs(C[i] - Co[i]).max() / np.abs(Co[i]).max())
-                 for i in range(len(Co)))
-        eu = float(np.abs(u - uo).max() / np.abs(uo).max())
-        out[prec] = {"rel_linf_C": eC, "rel_linf_u": eu, "steps": steps}
-        sim.close()
-    return out
-
-
-def cpu_baseline(wl, steps):
-    """The FP64 oracle, untuned, on a bounded sample of the same workload:
-    `steps` time steps of the full 512 x 512 box, one thread."""
-    import warnings
-
-    from threadpoolctl import threadpool_limits
-
-    import oracle
-    warnings.simplefilter("ignore")
-    with threadpool_limits(limits=1):
-        prm, geo, st = oracle.from_workload(wl)
-        t = time.perf_counter()
-        oracle.run(prm, geo, st, steps)
-        dt = time.perf_counter() - t
-    return {"value": wl.nodes * steps / dt / 1e6, "unit": "MLUPS",
-            "cores": 1, "kind": "oracle",
-            "sample": "%d steps of the full %dx%d N=%d box, numpy float64, "
-                      "1 thread, %.1f s" % (steps, wl.shape[1], wl.shape[0],
-                                             wl.nphase, dt)}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20000)
-    ap.add_argument("--warmup", type=int, default=200)
-    ap.add_argument("--n", type=int, default=512)
-    ap.add_argument("--cpu-steps", type=int, default=64)
-    ap.add_argument("--skip-cpu", action="store_true")
-    ap.add_argument("--tile", type=int, default=0)
-    ap.add_argument("--sphere", type=int, default=256,
-                    help="also time the 3D sphere box at this n (0: skip)")
-    ap.add_argument("--sphere-steps", type=int, default=100)
+    ap.add_argument("--steps", type=int, default=200,
+                    help="timed steps of the headline (256^3 FP32)")
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--n", type=int, default=HEAD_N,
+                    help="edge of the headline's 3D box")
+    ap.add_argument("--leg-steps", type=int, default=50,
+                    help="timed steps of the other 3D precisions")
+    ap.add_argument("--porous-steps", type=int, default=2000)
+    ap.add_argument("--cpu-steps", type=int, default=40)
+    ap.add_argument("--err-steps", type=int, default=40,
+                    help="steps of the reduced boxes for the error columns")
+    ap.add_argument("--samples", type=int, default=12,
+                    help="sampled nodes of the full-size one-step check")
+    ap.add_argument("--skip-cpu", action="store_true",
+                    help="no oracle (no cpu_baseline, no error columns)")
     ap.add_argument("--batch", type=int, default=256,
                     help="also time this many batched instances (0: skip)")
     ap.add_argument("--batch-steps", type=int, default=200)
@@ -487,21 +623,22 @@ def main():
                     help="also time the adjoint sweep on the n x n channel "
                          "(0: skip)")
     ap.add_argument("--adjoint-steps", type=int, default=2000)
+    ap.add_argument("--precisions", default="fp32,fp64,fp16,bf16",
+                    help="3D precisions to time (the first is not repeated)")
+    ap.add_argument("--no-2d", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--sweep", metavar="OUT_JSON", nargs="?", const="",
                     default=None,
                     help="run only the 2D roofline sweep over grid sizes, "
                          "phase counts and precisions")
-    ap.add_argument("--traffic-summary", nargs=2, metavar=("FETCH_DIR",
-                                                           "WRITE_DIR"),
+    ap.add_argument("--traffic-summary", nargs=4,
+                    metavar=("FETCH_DIR", "WRITE_DIR", "KIND", "PRECISION"),
                     help="write profiles/hbm_traffic.json from two "
-                         "rocprofv3 counter runs (no GPU needed)")
-    ap.add_argument("--precision", default="both",
-                    choices=["both", "fp32", "fp64"])
+                         "rocprofv3 counter runs (no GPU needed); KIND is "
+                         "3d or 2d")
     a = ap.parse_args()
     if a.traffic_summary:
-        traffic_summary(a.traffic_summary[0], a.traffic_summary[1],
-                        "fp64" if a.precision == "fp64" else "fp32", a.n)
+        traffic_summary(*a.traffic_summary)
         return 0
     if a.gpus != 1:
         print("bench.py runs on one GPU only: the library has no multi-GPU "
@@ -516,49 +653,64 @@ def main():
     if a.sweep is not None:
         sweep(torch, a.sweep or None)
         return 0
-    wl = make_workload(a.n)
-    N = wl.nphase
-    res = {}
+    from paper_2311_10314_amd import workloads as W
     if a.copy_calibration:
         copy_calibration(torch)
-    precs = (("fp32", 4), ("fp64", 8))
-    if a.precision != "both":
-        precs = tuple(x for x in precs if x[0] == a.precision)
-    for prec, esz in precs:
-        print("timing %s: %d warmup + %d steps on %s" % (prec, a.warmup,
-                                                         a.steps, wl.shape),
+
+    # ---- headline: 3D box, FP32 ------------------------------------------
+    wl = W.droplet_impact_sphere_3d(n=a.n)
+    precs = [p for p in a.precisions.split(",") if p]
+    head_prec = precs[0]
+    print("headline: %s %s, %d warmup + %d steps" % (
+        wl.name, "x".join(map(str, wl.shape)), a.warmup, a.steps),
+        file=sys.stderr, flush=True)
+    sim, ms, drift = time_gpu(wl, head_prec, a.steps, a.warmup, torch)
+    sampled = None
+    if not a.skip_cpu and a.samples > 0:
+        sampled = sampled_full_size_error(wl, sim, a.samples)
+        print("  full-size sampled one-step check: %s" % sampled,
               file=sys.stderr, flush=True)
-        sim, ms, drift = time_gpu(wl, prec, a.steps, a.warmup, torch,
-                                  a.tile)
-        sim.close()
-        bpn = algorithmic_bytes_per_node(N, 2, 9, 9, prec)
-        per_launch = bpn * wl.nodes
-        achieved = per_launch / (ms * 1e-3) / 1e9
-        traffic = measured_traffic(prec)
-        copy = copy_rate(torch, per_launch)
-        res[prec] = {
-            "value": wl.nodes / (ms * 1e-3) / 1e6,
-            "set_mlups": (N + 1) * wl.nodes / (ms * 1e-3) / 1e6,
-            "ms_per_step": ms,
-            "mass_drift": drift,
-            "roofline": {"bound": "hbm", "achieved": achieved,
-                         "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": achieved / HBM_PEAK_GBS,
-                         "traffic": traffic,
-                         "copy_GBs": copy,
-                         "frac_of_copy": achieved / copy,
-                         "algorithmic_bytes_per_launch": per_launch,
-                         "bytes_per_node": bpn},
-        }
-        print("  %s: %.4f ms/step, %.0f MLUPS, %.0f GB/s (copy of the same "
-              "bytes: %.0f GB/s)" % (prec, ms, res[prec]["value"], achieved,
-                                    copy), file=sys.stderr, flush=True)
-    sphere = None
-    if a.sphere:
-        print("timing the 3D sphere box at %d^3" % a.sphere, file=sys.stderr,
+    sim.close()
+    head_roof = roofline("3d", head_prec, wl.nodes, ms, 2, 3, 15, 19, torch)
+    print("  %s: %.4f ms/step, %.0f MLUPS, %.0f GB/s algorithmic "
+          "(%.3f of peak)" % (head_prec, ms, wl.nodes / (ms * 1e-3) / 1e6,
+                              head_roof["achieved"], head_roof["frac"]),
+          file=sys.stderr, flush=True)
+    legs3 = {}
+    for prec in precs[1:]:
+        s2, ms2, dr2 = time_gpu(wl, prec, a.leg_steps, a.warmup, torch)
+        s2.close()
+        legs3[prec] = {"value": wl.nodes / (ms2 * 1e-3) / 1e6,
+                       "unit": "MLUPS", "ms_per_step": ms2,
+                       "steps": a.leg_steps, "mass_drift": dr2,
+                       "roofline": roofline("3d", prec, wl.nodes, ms2, 2, 3,
+                                            15, 19, torch)}
+        print("  %s: %.4f ms/step" % (prec, ms2), file=sys.stderr,
               flush=True)
-        sphere = sphere_leg(a.sphere, a.sphere_steps, 10, torch,
-                            tuple(p for p, _ in precs) + ("fp16", "bf16"))
+
+    # ---- 2D porous box (cache-resident) ------------------------------------
+    wl2 = W.porous_bands_2d(n=512)
+    porous = None
+    if not a.no_2d:
+        porous = {"workload": "porous_bands_2d 512x512, N=3 (+1 flow set), "
+                              "D2Q9, 40 disks, rho 1:10:100",
+                  "cache_resident": True,
+                  "note": "about 110 MB (FP32) / 205 MB (FP64) per step fit "
+                          "the 256 MB memory-side cache: not an HBM "
+                          "roofline measurement"}
+        for prec in ("fp32", "fp64"):
+            s2, ms2, dr2 = time_gpu(wl2, prec, a.porous_steps, 50, torch)
+            s2.close()
+            r = roofline("2d", prec, wl2.nodes, ms2, 3, 2, 9, 9, torch)
+            r["bound"] = "cache"
+            porous[prec] = {"value": wl2.nodes / (ms2 * 1e-3) / 1e6,
+                            "set_mlups": 4 * wl2.nodes / (ms2 * 1e-3) / 1e6,
+                            "unit": "MLUPS", "ms_per_step": ms2,
+                            "steps": a.porous_steps, "mass_drift": dr2,
+                            "roofline": r}
+            print("  porous 512^2 %s: %.4f ms/step" % (prec, ms2),
+                  file=sys.stderr, flush=True)
+
     batched = None
     if a.batch:
         print("timing %d batched instances" % a.batch, file=sys.stderr,
@@ -569,35 +721,55 @@ def main():
         print("timing the adjoint sweep on the %d^2 channel" % a.adjoint,
               file=sys.stderr, flush=True)
         adjoint = adjoint_leg(a.adjoint, a.adjoint_steps, 100, torch)
-    err = None
+
+    # ---- cpu_baseline leg: the oracle, and the error columns ---------------
     cpu = None
+    err = None
     if not a.skip_cpu:
-        print("error vs oracle (10 steps) and cpu baseline", file=sys.stderr,
-              flush=True)
-        err = error_vs_oracle(wl, 10)
-        cpu = cpu_baseline(wl, a.cpu_steps)
-    if "fp32" not in res:
-        print(json.dumps({"fp64": res["fp64"], "sphere3d": sphere,
-                          "batched": batched, "adjoint": adjoint}))
-        return 0
-    f32 = res["fp32"]
+        small = W.droplet_impact_sphere_3d(n=REDUCED_N)
+        print("cpu baseline: oracle on %s %s, %d steps, one core" % (
+            small.name, "x".join(map(str, small.shape)), a.cpu_steps),
+            file=sys.stderr, flush=True)
+        cpu, ref = oracle_leg(small, a.cpu_steps, wl2, 10,
+                              a.batch if batched else 0)
+        for prec in precs:
+            e = gpu_errors(small, prec, a.cpu_steps, ref["sphere"], torch)
+            e["oracle_mass_drift"] = ref["sphere_drift"]
+            if prec == head_prec:
+                err = {"reduced_box": e, "full_size_sampled": sampled}
+            else:
+                legs3[prec]["error_vs_oracle"] = e
+            print("  %s error on the reduced box: %s" % (prec, e),
+                  file=sys.stderr, flush=True)
+        if porous:
+            for prec in ("fp32", "fp64"):
+                porous[prec]["error_vs_oracle"] = gpu_errors(
+                    wl2, prec, 10, ref["porous"], torch)
+        if batched:
+            batched["error_vs_oracle"] = batch_errors(ref["batch"],
+                                                      a.batch, torch)
     line = {
-        "metric": METRIC, "value": f32["value"], "unit": "MLUPS",
+        "metric": METRIC,
+        "value": wl.nodes / (ms * 1e-3) / 1e6, "unit": "MLUPS",
         "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
-        "ms_per_step": f32["ms_per_step"], "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": {"fp32": "f32", "fp64": "f64",
+                                       "fp16": "f32", "bf16": "f32"}[head_prec],
         "data": "synthetic",
-        "config": {"workload": "porous_bands_2d: %dx%d periodic, N=3 "
-                               "(+1 flow set), D2Q9, 40 disks, rho 1:10:100"
-                               % (a.n, a.n),
-                   "nodes": wl.nodes, "phases": N, "precision": "fp32"},
-        "set_mlups": f32["set_mlups"],
-        "mass_drift": f32["mass_drift"],
-        "roofline": f32["roofline"],
+        "config": {"workload": "droplet_impact_sphere_3d: %d^3 periodic, "
+                               "N=2 phase sets (D3Q15) + flow set (D3Q19), "
+                               "sphere R=%g, droplet R=%g at 0.02, rho "
+                               "10:1, %s storage" % (
+                                   a.n, 60 * a.n / 256, 40 * a.n / 256,
+                                   head_prec),
+                   "nodes": wl.nodes, "phases": 2, "precision": head_prec},
+        "set_mlups": 3 * wl.nodes / (ms * 1e-3) / 1e6,
+        "mass_drift": drift,
+        "roofline": head_roof,
         "cpu_baseline": cpu,
         "error_vs_oracle": err,
-        "fp64": res.get("fp64"),
-        "sphere3d": sphere,
+        "sphere3d": legs3,
+        "porous2d": porous,
         "batched": batched,
         "adjoint": adjoint,
     }
