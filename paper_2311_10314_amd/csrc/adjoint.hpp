@@ -85,11 +85,15 @@ hipError_t launch_adj_seed(const Coef<double>& kd, int phase,
                            hipStream_t st);
 
 // dJ/dcos theta_iN = dJ/dE_i |grad psi| into gcos [N-1][n], and dJ/dpsi
-// into gpsi_out [n] (ggpsi is updated in place on the way).
+// into gpsi_out [n] (ggpsi is updated in place on the way). psi64 / cos64
+// (may be NULL): the float64 psi [n] and cos theta_iN [N-1][n] the wetting
+// weights were made from; used for the derivative of E_i in psi instead of
+// the stored psi and E_i.
 template <class S>
 hipError_t launch_adj_finish(const Coef<double>& kd, int nm1, const S* psi,
-                             const S* wet, const double* gE, double* ggpsi,
-                             const double* gpsi, double* gcos,
+                             const S* wet, const double* psi64,
+                             const double* cos64, const double* gE,
+                             double* ggpsi, const double* gpsi, double* gcos,
                              double* gpsi_out, hipStream_t st);
 
 }  // namespace ddcc

@@ -806,6 +806,29 @@ __global__ __launch_bounds__(kThreads) void k_adj_finish1(Coef<double> kd,
   ggpsi[n + x] += coef * g1;
 }
 
+// The same from the float64 psi and cosines: dE_i / d(grad psi) =
+// cos theta_iN grad psi / |grad psi|.
+__global__ __launch_bounds__(kThreads) void k_adj_finish1_f64(
+    Coef<double> kd, int nm1, const double* psi64, const double* cos64,
+    const double* gE, double* ggpsi, double* gcos) {
+  const long long n = kd.n;
+  const long long x = (long long)blockIdx.x * kThreads + threadIdx.x;
+  if (x >= n) return;
+  const int gx = int(x % kd.nx), gy = int(x / kd.nx);
+  const Nb3 b = nb3(gx, gy, kd.nx, kd.ny);
+  const P3<double> ps = load3<double>(psi64, b);
+  const double g0 = gx3(ps), g1 = gy3(ps);
+  const double mag = sqrt(g0 * g0 + g1 * g1);
+  double coef = 0.0;
+  for (int i = 0; i < nm1; ++i) {
+    const double ge = gE[(long long)i * n + x];
+    gcos[(long long)i * n + x] = ge * mag;
+    if (mag > 0.0) coef += ge * cos64[(long long)i * n + x] / mag;
+  }
+  ggpsi[x] += coef * g0;
+  ggpsi[n + x] += coef * g1;
+}
+
 __global__ __launch_bounds__(kThreads) void k_adj_finish2(Coef<double> kd,
                                                           const double* ggpsi,
                                                           const double* gpsi,
@@ -875,12 +898,17 @@ hipError_t launch_adj_seed(const Coef<double>& kd, int phase,
 
 template <class S>
 hipError_t launch_adj_finish(const Coef<double>& kd, int nm1, const S* psi,
-                             const S* wet, const double* gE, double* ggpsi,
-                             const double* gpsi, double* gcos,
+                             const S* wet, const double* psi64,
+                             const double* cos64, const double* gE,
+                             double* ggpsi, const double* gpsi, double* gcos,
                              double* gpsi_out, hipStream_t st) {
   const dim3 g(blocks_for(kd.n)), t(kThreads);
-  hipLaunchKernelGGL((k_adj_finish1<S>), g, t, 0, st, kd, nm1, psi, wet, gE,
-                     ggpsi, gcos);
+  if (psi64 && cos64)
+    hipLaunchKernelGGL(k_adj_finish1_f64, g, t, 0, st, kd, nm1, psi64, cos64,
+                       gE, ggpsi, gcos);
+  else
+    hipLaunchKernelGGL((k_adj_finish1<S>), g, t, 0, st, kd, nm1, psi, wet, gE,
+                       ggpsi, gcos);
   hipLaunchKernelGGL(k_adj_finish2, g, t, 0, st, kd, ggpsi, gpsi, gpsi_out);
   return hipGetLastError();
 }
@@ -895,10 +923,10 @@ hipError_t launch_adj_finish(const Coef<double>& kd, int nm1, const S* psi,
                                          const AdjFwd<S>&, int,               \
                                          const double*, double*, int,         \
                                          hipStream_t);                        \
-  template hipError_t launch_adj_finish<S>(const Coef<double>&, int, const S*, \
-                                           const S*, const double*, double*,  \
-                                           const double*, double*, double*,   \
-                                           hipStream_t);
+  template hipError_t launch_adj_finish<S>(                                   \
+      const Coef<double>&, int, const S*, const S*, const double*,            \
+      const double*, const double*, double*, const double*, double*, double*, \
+      hipStream_t);
 DDCC_ADJ_INST(double)
 DDCC_ADJ_INST(float)
 

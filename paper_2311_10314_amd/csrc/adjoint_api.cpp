@@ -332,9 +332,13 @@ int adjoint_as(ddcc_ctx* c, int64_t nsteps, int interval, int phase,
     ACHK(hipEventRecord(pp.freed[b], c->stream), "event");
   }
 
+  // the derivative of the wetting weights in psi from the float64 geometry
+  // the weights were made from
+  const double* psi64 = c->geo64;
+  const double* cos64 = psi64 ? psi64 + n : nullptr;
   ACHK(launch_adj_finish<S>(c->kd, N - 1, static_cast<const S*>(c->psi),
-                            static_cast<const S*>(c->wet), gE, ggpsi, gpsi,
-                            gcos, gpsi_out, c->stream),
+                            static_cast<const S*>(c->wet), psi64, cos64, gE,
+                            ggpsi, gpsi, gcos, gpsi_out, c->stream),
        "gradient kernels");
   if (gcos_host)
     ACHK(hipMemcpyAsync(gcos_host, gcos, (size_t)(N - 1) * n * sizeof(double),

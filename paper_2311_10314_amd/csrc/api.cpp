@@ -367,7 +367,7 @@ void release(ddcc_ctx* c) {
                   c->g[1],  c->T[0],   c->T[1],     c->hist,  c->psi,
                   c->wet,   c->staging, c->partial, c->bad,  c->work,
                   c->diag_partial, c->diag_bad, c->diag_first,
-                  c->dkd,   c->dkf};
+                  c->dkd,   c->dkf,    c->geo64};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
@@ -579,6 +579,27 @@ static int geometry_from_device(ddcc_ctx* c, int K, const double* psik,
                                     static_cast<float*>(c->wet), c->n, 0,
                                     c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "geometry kernel");
+  // The adjoint's derivative of the wetting weights E_i = cos theta_iN
+  // |grad psi| with respect to psi is cos theta_iN grad psi / |grad psi|,
+  // taken from the float64 psi and cosines: a float32 psi rounds to 1 a few
+  // cells off a wall, where grad psi is small but not zero, and E_i / |grad
+  // psi| mixes two evaluations of |grad psi| that differ in their rounding
+  // where psi is 1 up to rounding. 2D contexts with one wall (those the
+  // adjoint supports) keep the float64 psi and cosines.
+  if (c->p.dim == 2 && K == 1) {
+    const size_t n = (size_t)c->n;
+    if (!c->geo64)
+      HIPCHK(c, hipMalloc(&c->geo64, (size_t)(nm1 + 1) * n * sizeof(double)),
+             "hipMalloc float64 geometry");
+    e = hipMemcpyAsync(c->geo64, psik, n * sizeof(double),
+                       hipMemcpyDeviceToDevice, c->stream);
+    if (e == hipSuccess)
+      e = ctk ? hipMemcpyAsync(c->geo64 + n, ctk, nm1 * n * sizeof(double),
+                               hipMemcpyDeviceToDevice, c->stream)
+              : hipMemsetAsync(c->geo64 + n, 0, nm1 * n * sizeof(double),
+                               c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "copy float64 geometry");
+  }
   c->geom_ok = true;
   c->nwalls = K;
   c->fields_ok = false;

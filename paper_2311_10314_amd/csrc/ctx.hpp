@@ -29,6 +29,9 @@ struct ddcc_ctx {
   void* psi = nullptr;
   void* wet = nullptr;         // wetting weights [N-1][n]
   double* work = nullptr;     // 3D: C_i and mu_i fields, 2 N n float64
+  // 2D contexts with one wall: psi [n] and cos theta_iN [N-1][n] in
+  // float64, for the adjoint's derivative of the wetting weights
+  double* geo64 = nullptr;
   double* staging = nullptr;  // (N + dim + 1) * n float64, lazily
   double* partial = nullptr;
   int* bad = nullptr;

@@ -2,10 +2,10 @@
 //
 // A step is three kernels on one stream:
 //   k_frac3d  pull the phase populations and sum them: phi C_i, then
-//             C_i = phi C_i / sum_j phi C_j, written as a float64 field;
+//             C_i = phi C_i / sum_j phi C_j, written as a field;
 //   k_mu3d    phi mu_i (eq. 2.14) from C_j and psi on the 18 D3Q19
 //             neighbours (div(psi grad C_j)) and the static wetting weights,
-//             mu_i = phi mu_i / psi_hat written as a float64 field (each
+//             mu_i = phi mu_i / psi_hat written as a field (each
 //             workgroup marches a column of tiles in z with three planes of
 //             C_j and psi in LDS);
 //   k_step3d  gradients of C_i, mu_i, psi and psi rho and the divergence of
@@ -19,13 +19,19 @@
 // workgroup a 64 x TY column of nodes over ZB planes and march it in z with
 // three planes of their stencil fields (C_j, psi; and mu_i for the step) in
 // an LDS ring, so each value is fetched once per tile instead of once per
-// neighbour. The C and mu fields cost 4 N float64 values of traffic per node
-// beyond the fused minimum; in return no halo is recomputed.
+// neighbour. The C and mu fields (in the field type: float64 for FP64
+// contexts, float32 otherwise) cost 4 N values of traffic per node beyond
+// the fused minimum; in return no halo is recomputed. (A single z-marching
+// kernel that pulls the phase populations of a two-node halo and evaluates
+// the chemical potential in LDS was 2.2x slower, and one that only folds
+// the chemical potential into the node update 1.25x slower: at the two
+// waves per SIMD the node update's registers allow, those stages'
+// latencies are not hidden.)
 //
 // Storage as in 2D: float64 rest populations of the phase sets in their own
 // plane, g_0 stored as g_0 - rho0, history phi C_i u (3N), Y (6), P in place,
 // T (xy, xz, yz) double-buffered. C, mu, psi rho and the chemical potential
-// are evaluated in float64 in both precisions.
+// are evaluated in float64 in every precision.
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
@@ -154,6 +160,14 @@ __device__ inline bool node_of(const int nx, const int ny, int& x, int& y,
   return x < nx && y < ny;
 }
 
+// The C and mu work fields between the kernels are kept in the field type S
+// (float64 for FP64 contexts, float32 otherwise): C_i and mu_i are formed in
+// float64 and rounded once when stored.
+template <class S>
+__device__ inline S* work_field(double* p) {
+  return reinterpret_cast<S*>(p);
+}
+
 // ---- k_frac3d -------------------------------------------------------------
 template <int N, class LF, class Pop, class S, class R, int MODE, int TY>
 __global__ __launch_bounds__(TX* TY) void k_frac3d(Coef<double> k,
@@ -189,7 +203,8 @@ __global__ __launch_bounds__(TX* TY) void k_frac3d(Coef<double> k,
   for (int i = 0; i < N; ++i) tot += psiC[i];
   const D inv = D(1) / (tot > k.psi_min ? tot : k.psi_min);
 #pragma unroll
-  for (int i = 0; i < N; ++i) stp(b.fC + (long long)i * k.n, idx, psiC[i] * inv);
+  for (int i = 0; i < N; ++i)
+    stp(work_field<S>(b.fC) + (long long)i * k.n, idx, S(psiC[i] * inv));
 }
 
 // ---- k_mu3d ---------------------------------------------------------------
@@ -240,7 +255,8 @@ __global__ __launch_bounds__(TX* TY) void k_mu3d(Coef<double> k, Bufs<Pop, S> b)
                            unsigned(wrap(x0 + lx - 1, nx));
       pl.p[ly][lx] = D(ldp(b.psi, idx));
 #pragma unroll
-      for (int j = 0; j < N; ++j) pl.c[j][ly][lx] = ldp(b.fC + (long long)j * k.n, idx);
+      for (int j = 0; j < N; ++j)
+        pl.c[j][ly][lx] = D(ldp(work_field<S>(b.fC) + (long long)j * k.n, idx));
     }
   };
 
@@ -304,7 +320,8 @@ __global__ __launch_bounds__(TX* TY) void k_mu3d(Coef<double> k, Bufs<Pop, S> b)
             grad += k.grad34[i][j] * L[j];
             wet += k.wet3[i][j] * W[j];
           }
-        stp(b.fmu + (long long)i * k.n, idx, (psi * bulk + grad + wet) / psih);
+        stp(work_field<S>(b.fmu) + (long long)i * k.n, idx,
+            S((psi * bulk + grad + wet) / psih));
       }
     }
     // the slot of plane z - 1 is overwritten by the next iteration's load
@@ -433,15 +450,21 @@ __device__ inline void step3d_node(const Coef<double>& kd, const Coef<R>& k,
     const R divT[3] = {-sgrad<1>(txy) - sgrad<2>(txz),
                        sgrad<0>(txy) - sgrad<2>(tyz),
                        sgrad<0>(txz) + sgrad<1>(tyz)};
-    R j[3] = {R(0), R(0), R(0)};
+    // sum_{p != 0} g_p and j = sum_p c_p g_p are accumulated in float64
+    // in every precision: both are small differences of populations of
+    // either sign (eq. 19, the velocity recovery), where float32 sums lose
+    // digits the stored populations still carry
+    D sg = D(0), jd[3] = {D(0), D(0), D(0)};
     static_for<0, QG>([&](auto pc) {
       constexpr int p = decltype(pc)::value;
       gp[p] = R(ldp(b.gA + (long long)p * n, nb.src(LG::c[p].x, LG::c[p].y, LG::c[p].z)));
-      if constexpr (p > 0) sum_gm += gp[p];
-      if constexpr (LG::c[p].x != 0) j[0] += R(LG::c[p].x) * gp[p];
-      if constexpr (LG::c[p].y != 0) j[1] += R(LG::c[p].y) * gp[p];
-      if constexpr (LG::c[p].z != 0) j[2] += R(LG::c[p].z) * gp[p];
+      if constexpr (p > 0) sg += D(gp[p]);
+      if constexpr (LG::c[p].x != 0) jd[0] += D(LG::c[p].x) * D(gp[p]);
+      if constexpr (LG::c[p].y != 0) jd[1] += D(LG::c[p].y) * D(gp[p]);
+      if constexpr (LG::c[p].z != 0) jd[2] += D(LG::c[p].z) * D(gp[p]);
     });
+    sum_gm = R(sg);
+    const R j[3] = {R(jd[0]), R(jd[1]), R(jd[2])};
     // force (eq. 3.13): -div T^{n-1} + sum_i phi mu_i grad C_i
     //                   + P^{n-1} grad psi + psi (rho a + G)
     const R Pprev = R(ldp(b.hist + (long long)(3 * N + 6) * n, idx));
@@ -677,8 +700,8 @@ void k_step3d(Coef<double> kda, Coef<R> ka,
       pl.p[ly][lx] = double(ldp(b.psi, i0));
 #pragma unroll
       for (int j = 0; j < N; ++j) {
-        pl.c[j][ly][lx] = ldp(b.fC + (long long)j * k.n, i0);
-        pl.m[j][ly][lx] = ldp(b.fmu + (long long)j * k.n, i0);
+        pl.c[j][ly][lx] = double(ldp(work_field<S>(b.fC) + (long long)j * k.n, i0));
+        pl.m[j][ly][lx] = double(ldp(work_field<S>(b.fmu) + (long long)j * k.n, i0));
       }
     }
   };

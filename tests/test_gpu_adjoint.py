@@ -5,8 +5,8 @@ centroid x of phase k); gradients with respect to the per-node angle field
 cos theta_iN and psi. Checked against
   * the oracle's reverse-mode derivative (oracle.adjoint, float64 autograd
     of the oracle step) from the same initial state: FP64 within 1e-9 of
-    the largest gradient entry; FP32 within 1e-4 (angles) and 1e-3 (psi, on
-    the wall layer of _wall_layer);
+    the largest gradient entry; FP32 within 1e-4 (angles and psi, over the
+    whole field);
   * central finite differences (Richardson-extrapolated) of the GPU FP64
     forward along random directions: within 1e-6 (the target is 1e-4);
 and for properties of the sweep: gradients independent of the checkpoint
@@ -33,11 +33,11 @@ def _rel(a, b):
 
 def _wall_layer(psi):
     """Nodes with psi >= 1e-2 whose 5 x 5 neighbourhood has no psi within
-    1e-6 of 1. The wetting term is weighted by |grad psi|, whose derivative
-    is grad psi / |grad psi|: of unit size however small grad psi is. Where
-    psi is within float32 rounding of 1, float32 storage makes grad psi
-    exactly 0 and drops that term, so a float32 context's psi gradient
-    differs there by design; it is compared on this mask."""
+    1e-6 of 1 (reported beside the whole-field error). The wetting term is
+    weighted by |grad psi|, whose derivative grad psi / |grad psi| is of
+    unit size however small grad psi is; a float32 psi would make grad psi
+    exactly 0 where psi is within float32 rounding of 1, so float32
+    contexts take that derivative from the float64 geometry."""
     near_one = np.zeros(psi.shape, bool)
     for dy in range(-2, 3):
         for dx in range(-2, 3):
@@ -75,10 +75,8 @@ def test_adjoint_matches_oracle(case, precision):
         assert abs(J - Jo) <= 1e-13 * abs(Jo)
         assert ec < 1e-9 and ep < 1e-9
     else:
-        # float32 storage of psi leaves grad psi an absolute error of about
-        # 6e-8, a relative 1e-3 where |grad psi| ~ 6e-5 in the layer's tail
         assert abs(J - Jo) <= 1e-6 * abs(Jo)
-        assert ec < 1e-4 and epm < 1e-3
+        assert ec < 1e-4 and ep < 1e-4
 
 
 def test_adjoint_matches_finite_differences():
@@ -147,7 +145,7 @@ def test_context_left_at_the_final_level():
     b = _sim(wl)
     b.step(7)
     assert a.time == b.time == 7
-    from paper_2311_10314_amd.ddcc import unpack_state
+    from tests.helpers import unpack_state
     sa, sb = unpack_state(a, a.save()), unpack_state(b, b.save())
     for key in ("f", "g", "hist", "T"):
         assert np.array_equal(sa[key], sb[key])
@@ -244,5 +242,9 @@ def test_adjoint_channel_full_size():
     print("fp32 vs fp64: J %.3e grad cos %.2e grad psi %.2e (wall layer, "
           "%d nodes: %.2e)" % (abs(J32 - J) / abs(J), ec, ep, m.sum(), epm),
           flush=True)
+    k = np.unravel_index(np.argmax(np.abs(gp32 - gp)), gp.shape)
+    print("largest psi-gradient difference at %s: psi %.17g (float32 %r), "
+          "fp64 %.6e fp32 %.6e" % (k, psi0[k], float(np.float32(psi0[k])),
+                                   gp[k], gp32[k]), flush=True)
     assert abs(J32 - J) <= 1e-5 * abs(J)
-    assert ec < 1e-4 and epm < 1e-3
+    assert ec < 1e-4 and ep < 1e-4
