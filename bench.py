@@ -47,14 +47,23 @@ KERNEL_SOURCES = {
 }
 # element bytes (populations, fields) per precision
 PREC_BYTES = {"fp64": (8, 8), "fp32": (4, 4), "fp16": (2, 4), "bf16": (2, 4)}
-# the step kernels' template arguments as rocprofv3 prints them
+# The kernels of one step, as rocprofv3 names them (the 3D step is three
+# launches: C_i from the pulled phase populations, the chemical potential,
+# the node update; the 16-bit instances appear under their mangled names).
 KERNEL_TAGS = {
-    ("3d", "fp32"): "k_step3d<2, ddcc::D3Q15, ddcc::D3Q19, float, float, float, 0, 4>",
-    ("3d", "fp64"): "k_step3d<2, ddcc::D3Q15, ddcc::D3Q19, double, double, double, 0, 4>",
-    ("3d", "fp16"): "k_step3d<2, ddcc::D3Q15, ddcc::D3Q19, _Float16, float, float, 0, 4>",
-    ("3d", "bf16"): "k_step3d<2, ddcc::D3Q15, ddcc::D3Q19, __bf16, float, float, 0, 4>",
-    ("2d", "fp32"): "k_step2d<3, float, float, float, 0, 8>",
-    ("2d", "fp64"): "k_step2d<3, double, double, double, 0, 4>",
+    ("3d", "fp32"): ["k_frac3d<2, ddcc::D3Q15, float, float, float, 0, 4>",
+                     "k_mu3d<2, float, float, 4>",
+                     "k_step3d<2, ddcc::D3Q15, ddcc::D3Q19, float, float, "
+                     "float, 0, 4>"],
+    ("3d", "fp64"): ["k_frac3d<2, ddcc::D3Q15, double, double, double, 0, 4>",
+                     "k_mu3d<2, double, double, 4>",
+                     "k_step3d<2, ddcc::D3Q15, ddcc::D3Q19, double, double, "
+                     "double, 0, 4>"],
+    ("3d", "fp16"): ["k_frac3dILi2ENS_5D3Q15EDF16_ffLi0ELi4E",
+                     "k_mu3dILi2EDF16_fLi4E",
+                     "k_step3dILi2ENS_5D3Q15ENS_5D3Q19EDF16_ffLi0ELi4E"],
+    ("2d", "fp32"): ["k_step2d<3, float, float, float, 0, 8>"],
+    ("2d", "fp64"): ["k_step2d<3, double, double, double, 0, 4>"],
 }
 HEAD_N = 256          # the 3D box of the headline
 REDUCED_N = 48        # the same generator at 48^3 for the oracle legs
@@ -165,20 +174,25 @@ def time_gpu(wl, precision, steps, warmup, torch, tile=0):
 
 
 
+COPY_RATE = True      # off in counter runs, whose 1 GiB calibration copy
+                      # must be the largest copy of the run
+
+
 def roofline(kind, precision, nodes, ms, N, dim, Qf, Qg, torch):
-    """Roofline object of one step kernel: algorithmic bytes of a launch
-    over its average duration, the bytes with the float64 rest planes, the
-    counter traffic (if taken on the current source) and the same-session
-    copy rate of the same bytes."""
+    """Roofline object of one step: algorithmic bytes of a step over its
+    average duration (HIP events around the timed steps on the library's
+    stream), the bytes with the float64 rest planes, the counter traffic (if
+    taken on the current source) and the same-session copy rate of the same
+    bytes."""
     bpn = algorithmic_bytes_per_node(N, dim, Qf, Qg, precision)
     bpn64 = algorithmic_bytes_per_node(N, dim, Qf, Qg, precision, True)
     per_launch = bpn * nodes
     achieved = per_launch / (ms * 1e-3) / 1e9
-    copy = copy_rate(torch, bpn64 * nodes)
+    copy = copy_rate(torch, bpn64 * nodes) if COPY_RATE else float("nan")
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
             "traffic": measured_traffic(kind, precision),
-            "kernel": KERNEL_TAGS.get((kind, precision)),
+            "kernels": KERNEL_TAGS.get((kind, precision)),
             "bytes_per_node": bpn,
             "algorithmic_bytes_per_launch": per_launch,
             "bytes_per_node_with_float64_rest": bpn64,
@@ -524,14 +538,22 @@ def sweep(torch, out_path=None):
     return rows
 
 
-def _counter_means(csv_path, counter, tag):
-    """Mean counter value (KiB per dispatch) of the kernel whose name
-    contains `tag`, and of the 1 GiB calibration copy (the largest
-    buffer-copy dispatch) in one rocprofv3 counter run."""
+def _counter_means(csv_path, counter, tags):
+    """Sum over the kernels of `tags` (name substrings) of the mean counter
+    value (KiB per dispatch), and the mean of the 1 GiB calibration copy
+    (the largest buffer-copy dispatch) in one rocprofv3 counter run."""
     import csv
     with open(csv_path) as fh:
         rows = [r for r in csv.DictReader(fh) if r["Counter_Name"] == counter]
-    step = [float(r["Counter_Value"]) for r in rows if tag in r["Kernel_Name"]]
+    step, nd = 0.0, []
+    for tag in tags:
+        v = [float(r["Counter_Value"]) for r in rows
+             if tag in r["Kernel_Name"]]
+        if not v:
+            raise SystemExit("%s: no %s dispatches of %s" % (csv_path,
+                                                               counter, tag))
+        step += sum(v) / len(v)
+        nd.append(len(v))
     # the 1 GiB calibration copies: the largest copy dispatches of the run
     # (the runtime's copy kernel keeps one grid size for all large copies,
     # so they are told apart by their counter values)
@@ -541,11 +563,10 @@ def _counter_means(csv_path, counter, tag):
     if copies:
         top = max(copies)
         copy = [v for v in copies if v >= 0.9 * top]
-    if not step or not copy or max(copy) < 1.0e5:
-        raise SystemExit("%s: no %s dispatches of %s or of the 1 GiB copy "
-                         "(run with --copy-calibration)"
-                         % (csv_path, counter, tag))
-    return sum(step) / len(step), sum(copy) / len(copy), len(step)
+    if not copy or max(copy) < 1.0e5:
+        raise SystemExit("%s: no %s dispatches of the 1 GiB copy (run with "
+                         "--copy-calibration)" % (csv_path, counter))
+    return step, sum(copy) / len(copy), nd
 
 
 def traffic_summary(fetch_dir, write_dir, kind, precision):
@@ -560,8 +581,7 @@ def traffic_summary(fetch_dir, write_dir, kind, precision):
     else:
         wl = W.porous_bands_2d(n=512)
         geom = (3, 2, 9, 9)
-    tag = KERNEL_TAGS[(kind, precision)].split("<")[0] + "<" + \
-        KERNEL_TAGS[(kind, precision)].split("<", 1)[1]
+    tag = KERNEL_TAGS[(kind, precision)]
     f_step, f_copy, nd = _counter_means(
         os.path.join(fetch_dir, "run_counter_collection.csv"), "FETCH_SIZE",
         tag)
@@ -655,6 +675,8 @@ def main():
         return 0
     from paper_2311_10314_amd import workloads as W
     if a.copy_calibration:
+        global COPY_RATE
+        COPY_RATE = False
         copy_calibration(torch)
 
     # ---- headline: 3D box, FP32 ------------------------------------------
