@@ -8,7 +8,7 @@
 namespace ddcc {
 
 // Stored forward state of one time level (read only in the reverse sweep),
-// laid out as the step's buffers: f [N][9][n] (plane 0 unused), f0 [N][n],
+// laid out as the step's buffers: f [N][8][n] (moving planes), f0 [N][n],
 // g [9][n], history [2N + 4][n] (phi C_i u, Y, P), T [n].
 template <class S>
 struct AdjFwd {

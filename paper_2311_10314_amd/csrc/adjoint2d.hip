@@ -150,7 +150,7 @@ __global__ __launch_bounds__(kThreads) void k_adj_frac(Coef<double> kd,
   for (int i = 0; i < N; ++i) {
     S mv = S(0);  // moving populations summed as the step sums them
 #pragma unroll
-    for (int p = 1; p < Q; ++p) mv += fw.f[(long long)(i * Q + p) * n + b.pull(p)];
+    for (int p = 1; p < Q; ++p) mv += phase_plane(fw.f, i, p, Q, n)[b.pull(p)];
     pc[i] = fw.f0[(long long)i * n + x] + double(mv);
     tot += pc[i];
   }
@@ -729,7 +729,8 @@ __global__ __launch_bounds__(kThreads) void k_adj_wsum(Coef<double> kd,
     const int gx = int(x % kd.nx), gy = int(x / kd.nx);
     const Nb3 b = nb3(gx, gy, kd.nx, kd.ny);
     S mv = S(0);
-    for (int p = 1; p < Q; ++p) mv += fw.f[(long long)(phase * Q + p) * n + b.pull(p)];
+    for (int p = 1; p < Q; ++p)
+      mv += phase_plane(fw.f, phase, p, Q, n)[b.pull(p)];
     const double pc = fw.f0[(long long)phase * n + x] + double(mv);
     sw += wgt[x] * pc;
     sm += pc;

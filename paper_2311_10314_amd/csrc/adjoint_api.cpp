@@ -62,7 +62,7 @@ struct Layout {
 Layout state_layout(const ddcc_ctx* c) {
   Layout L;
   const size_t n = (size_t)c->n;
-  L.sf = (size_t)c->p.nphase * c->Qf * n * c->pesz;
+  L.sf = (size_t)c->p.nphase * (c->Qf - 1) * n * c->pesz;
   L.s0 = (size_t)c->p.nphase * n * sizeof(double);
   L.sg = (size_t)c->Qg * n * c->pesz;
   L.sh = (size_t)c->nhist * n * c->esz;
@@ -85,7 +85,7 @@ hipError_t save_state(ddcc_ctx* c, char* slot, const Layout& L) {
     void* dev;
     size_t off, bytes;
   } parts[5] = {
-      {c->f[c->cur], 0, (size_t)c->p.nphase * c->Qf * n * c->pesz},
+      {c->f[c->cur], 0, (size_t)c->p.nphase * (c->Qf - 1) * n * c->pesz},
       {c->f0[c->cur], L.sf, (size_t)c->p.nphase * n * sizeof(double)},
       {c->g[c->cur], L.sf + L.s0, (size_t)c->Qg * n * c->pesz},
       {c->hist, L.sf + L.s0 + L.sg, (size_t)c->nhist * n * c->esz},

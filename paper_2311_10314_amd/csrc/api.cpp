@@ -508,7 +508,7 @@ int ddcc_create(const ddcc_params* p, void* stream, ddcc_ctx** out) {
   fill_coef<double>(c->p, c->n, c->kd);
   fill_coef<float>(c->p, c->n, c->kf);
   const size_t n = (size_t)c->n;
-  const size_t sf = (size_t)p->nphase * c->Qf * n * c->pesz;
+  const size_t sf = (size_t)p->nphase * (c->Qf - 1) * n * c->pesz;
   const size_t sg = (size_t)c->Qg * n * c->pesz;
   const size_t sT = (size_t)c->nT * n * c->esz;
   hipError_t e = hipSuccess;
@@ -537,10 +537,6 @@ int ddcc_create(const ddcc_params* p, void* stream, ddcc_ctx** out) {
     e = hipMemcpy(c->dkd, &c->kd, sizeof(Coef<double>), hipMemcpyHostToDevice);
   if (e == hipSuccess)
     e = hipMemcpy(c->dkf, &c->kf, sizeof(Coef<float>), hipMemcpyHostToDevice);
-  // plane 0 of the phase buffers is never written by the kernels (the rest
-  // populations live in f0): zero it so that checkpoints are deterministic
-  for (int a = 0; a < 2 && e == hipSuccess; ++a)
-    e = hipMemsetAsync(c->f[a], 0, sf, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) {
     release(c);
@@ -828,7 +824,7 @@ int ddcc_save(ddcc_ctx* c, void* buf, size_t* bytes) {
   if (!c || !bytes) return fail(c, DDCC_E_INVAL, "NULL argument");
   if (!c->fields_ok) return fail(c, DDCC_E_STATE, "init_fields first");
   const size_t n = (size_t)c->n;
-  const size_t sf = (size_t)c->p.nphase * c->Qf * n * c->pesz;
+  const size_t sf = (size_t)c->p.nphase * (c->Qf - 1) * n * c->pesz;
   const size_t sg = (size_t)c->Qg * n * c->pesz;
   const size_t sh = (size_t)c->nhist * n * c->esz;
   const size_t sT = (size_t)c->nT * n * c->esz;
@@ -840,7 +836,7 @@ int ddcc_save(ddcc_ctx* c, void* buf, size_t* bytes) {
   }
   if (*bytes < need) return fail(c, DDCC_E_INVAL, "buffer too small");
   SaveHeader h{};
-  std::memcpy(h.magic, "DDCCSAV2", 8);
+  std::memcpy(h.magic, "DDCCSAV3", 8);
   h.dim = c->p.dim;
   h.nx = c->p.nx;
   h.ny = c->p.ny;
@@ -880,7 +876,7 @@ int ddcc_load(ddcc_ctx* c, const void* buf, size_t bytes) {
   if (!c || !buf) return fail(c, DDCC_E_INVAL, "NULL argument");
   if (!c->geom_ok) return fail(c, DDCC_E_STATE, "init_geometry first");
   const size_t n = (size_t)c->n;
-  const size_t sf = (size_t)c->p.nphase * c->Qf * n * c->pesz;
+  const size_t sf = (size_t)c->p.nphase * (c->Qf - 1) * n * c->pesz;
   const size_t sg = (size_t)c->Qg * n * c->pesz;
   const size_t sh = (size_t)c->nhist * n * c->esz;
   const size_t sT = (size_t)c->nT * n * c->esz;
@@ -889,7 +885,7 @@ int ddcc_load(ddcc_ctx* c, const void* buf, size_t bytes) {
   if (bytes < need) return fail(c, DDCC_E_INVAL, "checkpoint too small");
   SaveHeader h;
   std::memcpy(&h, buf, sizeof(h));
-  if (std::memcmp(h.magic, "DDCCSAV2", 8) != 0 || h.dim != c->p.dim ||
+  if (std::memcmp(h.magic, "DDCCSAV3", 8) != 0 || h.dim != c->p.dim ||
       h.nx != c->p.nx || h.ny != c->p.ny || h.nz != c->p.nz ||
       h.nphase != c->p.nphase || h.lattice_f != c->p.lattice_f ||
       h.lattice_g != c->p.lattice_g || h.precision != c->p.precision ||
@@ -1008,7 +1004,7 @@ int ddcc_autotune(ddcc_ctx* c, int steps, int* ty_out) {
   const size_t n = (size_t)c->n;
   const int N = c->p.nphase;
   const int cur0 = c->cur;
-  const size_t sizes[5] = {(size_t)N * c->Qf * n * c->pesz,
+  const size_t sizes[5] = {(size_t)N * (c->Qf - 1) * n * c->pesz,
                            (size_t)N * n * sizeof(double),
                            (size_t)c->Qg * n * c->pesz,
                            (size_t)c->nT * n * c->esz,
@@ -1416,7 +1412,7 @@ int ddcc_batch_create(const ddcc_params* p, int count, const int* nx,
   const size_t nt = (size_t)b->ntot;
   hipError_t e = hipSuccess;
   for (int a = 0; a < 2 && e == hipSuccess; ++a) {
-    e = hipMalloc(&b->f[a], (size_t)N * kBatchQ * nt * b->pesz);
+    e = hipMalloc(&b->f[a], (size_t)N * (kBatchQ - 1) * nt * b->pesz);
     if (e == hipSuccess) e = hipMalloc(&b->f0[a], (size_t)N * nt * sizeof(double));
     if (e == hipSuccess) e = hipMalloc(&b->g[a], (size_t)kBatchQ * nt * b->pesz);
     if (e == hipSuccess) e = hipMalloc(&b->T[a], nt * b->esz);
@@ -1686,7 +1682,7 @@ int ddcc_batch_autotune(ddcc_batch* b, int steps, int* ty_out) {
   // The trial steps change the state: keep a copy of the current level.
   const int N = b->p.nphase;
   const size_t nt = (size_t)b->ntot;
-  const size_t sizes[5] = {(size_t)N * kBatchQ * nt * b->pesz,
+  const size_t sizes[5] = {(size_t)N * (kBatchQ - 1) * nt * b->pesz,
                            (size_t)N * nt * sizeof(double),
                            (size_t)kBatchQ * nt * b->pesz, nt * b->esz,
                            (size_t)nhist_of(N) * nt * b->esz};

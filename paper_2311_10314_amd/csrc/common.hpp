@@ -30,6 +30,15 @@ __device__ inline T ldp(const T* plane, unsigned i) {
                                      i * unsigned(sizeof(T)));
 }
 
+// Plane of the moving population p >= 1 of phase set i: the phase sets keep
+// only their Q - 1 moving planes, [N][Q-1][n]; their rest populations live
+// in the float64 plane f0.
+template <class T>
+__host__ __device__ inline T* phase_plane(T* f, int i, int p, int Q,
+                                          long long n) {
+  return f + ((long long)i * (Q - 1) + (p - 1)) * n;
+}
+
 template <class T>
 __device__ inline void stp(T* plane, unsigned i, T v) {
   *reinterpret_cast<T*>(reinterpret_cast<char*>(plane) + i * unsigned(sizeof(T))) = v;

@@ -17,7 +17,7 @@ enum { MODE_STEP = 0, MODE_INIT = 1, MODE_MOMENTS = 2 };
 // g_p); S that of the history, T and geometry fields.
 template <class Pop, class S>
 struct Bufs {
-  const Pop* fA;   // phase populations [N][Q][n]; plane p = 0 unused
+  const Pop* fA;   // moving phase populations [N][Q-1][n] (phase_plane)
   Pop* fB;
   const double* f0A;  // rest populations of the phase sets [N][n], float64
   double* f0B;
@@ -113,7 +113,7 @@ hipError_t launch_fill_u32(unsigned* dst, unsigned v, long long count,
                            hipStream_t st);
 
 // Per-phase sums of all populations (rest plane f0 [N][stride_n] plus
-// planes p >= 1 of f [N][Q][stride_n], nodes [0, n) of each plane) into
+// the moving planes of f [N][Q-1][stride_n], nodes [0, n) of each plane) into
 // partial[block * N + i], plus a non-finite flag per block in bad[block].
 template <class Pop>
 hipError_t launch_mass(const double* f0, const Pop* f, int nphase, int Q,

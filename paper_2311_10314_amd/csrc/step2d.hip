@@ -191,13 +191,13 @@ struct Step2D {
       for (int i = 0; i < N; ++i) {
         // phi C_i = sum_p f^i_p (Section 3); the rest population does not
         // move and lives in the float64 plane
-        const Pop* f = b.fA + (long long)i * Q * gd.n;
         // moving populations summed in the storage precision, the float64
         // rest population added last
         R mv = R(0);
 #pragma unroll
         for (int p = 1; p < Q; ++p) {
-          const R v = R(ldp(f + (long long)(p) * gd.n, nb.src(D2Q9::c[p].x, D2Q9::c[p].y)));
+          const R v = R(ldp(phase_plane(b.fA, i, p, Q, gd.n),
+                            nb.src(D2Q9::c[p].x, D2Q9::c[p].y)));
           if constexpr (KEPT) (*keep)[i][p] = v;
           mv += v;
         }
@@ -541,15 +541,13 @@ struct Step2D {
     for (int i = 0; i < N; ++i) {
       const R X[2] = {R(psiC[i]) * u[0], R(psiC[i]) * u[1]};
       const R em = k.eta[i] * psimu[i];
-      const Pop* fsrc = b.fA + (long long)i * Q * n;
-      Pop* fdst = b.fB + (long long)i * Q * n;
       if constexpr (MODE == MODE_INIT) {
         D comp = D(0);
 #pragma unroll
         for (int p = 1; p < Q; ++p) {
           const int cx = D2Q9::c[p].x, cy = D2Q9::c[p].y;
           const R feq = k.wf[p] * (em + (R(cx) * X[0] + R(cy) * X[1]) * k.inv_cs2);
-          stp(fdst + (long long)(p) * n, nb.src(cx, cy), narrow<Pop>(feq, comp));
+          stp(phase_plane(b.fB, i, p, Q, n), nb.src(cx, cy), narrow<Pop>(feq, comp));
         }
         // f^eq_0 = (w_0 - 1) eta phi mu + phi C (float64 rest plane), plus
         // the storage rounding of the moving populations
@@ -579,13 +577,15 @@ struct Step2D {
           if constexpr (KEPT)
             fp[p] = (*kept)[i][p];
           else
-            fp[p] = R(ldp(fsrc + (long long)(p) * n, nb.src(D2Q9::c[p].x, D2Q9::c[p].y)));
+            fp[p] = R(ldp(phase_plane(b.fA, i, p, Q, n),
+                          nb.src(D2Q9::c[p].x, D2Q9::c[p].y)));
         R del[Q];
         collide_phase<D2Q9>(fp, em, X, V, k.sf, k.cs2, del);
         D comp = D(0);
 #pragma unroll
         for (int p = 1; p < Q; ++p)
-          stp(fdst + (long long)(p) * n, idx, narrow<Pop>(fp[p] - del[p], comp));
+          stp(phase_plane(b.fB, i, p, Q, n), idx,
+              narrow<Pop>(fp[p] - del[p], comp));
         stp(b.f0B + (long long)(i) * n, idx,
             ldp(b.f0A + (long long)(i) * n, idx) - D(del[0]) + comp);
       }

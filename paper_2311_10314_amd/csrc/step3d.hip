@@ -188,11 +188,11 @@ __global__ __launch_bounds__(TX* TY) void k_frac3d(Coef<double> k,
     for (int i = 0; i < N; ++i) {
       // phi C_i = sum_p f^i_p (Section 3): moving populations summed in
       // the storage precision, the float64 rest population added last
-      const Pop* f = b.fA + (long long)i * QF * k.n;
       R mv = R(0);
       static_for<1, QF>([&](auto pc) {
         constexpr int p = decltype(pc)::value;
-        mv += R(ldp(f + (long long)p * k.n, nb.src(LF::c[p].x, LF::c[p].y, LF::c[p].z)));
+        mv += R(ldp(phase_plane(b.fA, i, p, QF, k.n),
+                    nb.src(LF::c[p].x, LF::c[p].y, LF::c[p].z)));
       });
       psiC[i] = ldp(b.f0A + (long long)i * k.n, idx) + D(mv);
     }
@@ -574,8 +574,6 @@ __device__ inline void step3d_node(const Coef<double>& kd, const Coef<R>& k,
   // ---- phase sets: equilibrium (3.5), source (3.6, 3.7), collision ---
 #pragma unroll
   for (int i = 0; i < N; ++i) {
-    const Pop* fsrc = b.fA + (long long)i * QF * n;
-    Pop* fdst = b.fB + (long long)i * QF * n;
     if constexpr (MODE == MODE_INIT) {
       const D psiC = psi_d * ldp(b.inC + (long long)i * n, idx);
       const R X[3] = {R(psiC) * u[0], R(psiC) * u[1], R(psiC) * u[2]};
@@ -586,7 +584,8 @@ __device__ inline void step3d_node(const Coef<double>& kd, const Coef<R>& k,
         constexpr int cx = LF::c[p].x, cy = LF::c[p].y, cz = LF::c[p].z;
         const R feq = k.wf[p] * (em + (R(cx) * X[0] + R(cy) * X[1] +
                                        R(cz) * X[2]) * k.inv_cs2);
-        stp(fdst + (long long)p * n, nb.src(cx, cy, cz), narrow<Pop>(feq, comp));
+        stp(phase_plane(b.fB, i, p, QF, n), nb.src(cx, cy, cz),
+            narrow<Pop>(feq, comp));
       });
       // f^eq_0 = (w_0 - 1) eta phi mu + phi C (float64 rest plane), plus
       // the storage rounding of the moving populations
@@ -603,7 +602,8 @@ __device__ inline void step3d_node(const Coef<double>& kd, const Coef<R>& k,
       R mv = R(0);
       static_for<1, QF>([&](auto pc) {
         constexpr int p = decltype(pc)::value;
-        fp[p] = R(ldp(fsrc + (long long)p * n, nb.src(LF::c[p].x, LF::c[p].y, LF::c[p].z)));
+        fp[p] = R(ldp(phase_plane(b.fA, i, p, QF, n),
+                      nb.src(LF::c[p].x, LF::c[p].y, LF::c[p].z)));
         mv += fp[p];
       });
       const D f0 = ldp(b.f0A + (long long)i * n, idx);
@@ -625,7 +625,8 @@ __device__ inline void step3d_node(const Coef<double>& kd, const Coef<R>& k,
       D comp = D(0);
 #pragma unroll
       for (int p = 1; p < QF; ++p)
-        stp(fdst + (long long)p * n, idx, narrow<Pop>(fp[p] - del[p], comp));
+        stp(phase_plane(b.fB, i, p, QF, n), idx,
+            narrow<Pop>(fp[p] - del[p], comp));
       stp(b.f0B + (long long)i * n, idx, f0 - D(del[0]) + comp);
 #pragma unroll
       for (int a = 0; a < 3; ++a) stp(b.hist + (long long)(3 * i + a) * n, idx, S(X[a]));

@@ -3,6 +3,7 @@
 
 #include <mutex>
 
+#include "common.hpp"
 #include "kernels.hpp"
 
 namespace ddcc {
@@ -39,10 +40,9 @@ __global__ __launch_bounds__(kMassThreads) void k_mass(const double* f0,
   for (long long x = (long long)blockIdx.x * kMassThreads + threadIdx.x; x < n;
        x += stride) {
     for (int i = 0; i < N; ++i) {
-      const S* fi = f + (long long)i * Q * stride_n + x;
       double s = f0[(long long)i * stride_n + x];
       for (int p = 1; p < Q; ++p) {
-        const double v = double(fi[(long long)p * stride_n]);
+        const double v = double(phase_plane(f, i, p, Q, stride_n)[x]);
         s += v;
       }
       if (!isfinite(s)) nonfinite = 1;

@@ -97,7 +97,7 @@ def test_non_finite_population_is_reported_by_the_mass_check():
     s = d.Sim.from_workload(wl, "fp64")
     buf = s.save()
     n = wl.nodes
-    npop = wl.nphase * 9 * n
+    npop = wl.nphase * 8 * n                # moving planes of the phase sets
     off = 56 + npop * 8 + 8 * 123          # rest plane of phase 0, node 123
     nan = np.frombuffer(np.array([np.nan]).tobytes(), np.uint8)
     bad = buf.copy()
@@ -145,7 +145,7 @@ def test_periodic_diagnostics_flag_a_non_finite_state():
     wl = W.random_small(2, 2, (20, 70), seed=1)
     s = d.Sim.from_workload(wl, "fp32")
     good = s.save()
-    npop = wl.nphase * 9 * wl.nodes
+    npop = wl.nphase * 8 * wl.nodes        # moving planes of the phase sets
     off = 56 + npop * 4 + 8 * 77           # rest plane (float64), node 77
     bad = good.copy()
     bad[off:off + 8] = np.frombuffer(np.array([np.inf]).tobytes(), np.uint8)
