@@ -629,7 +629,7 @@ def main():
     ap.add_argument("--leg-steps", type=int, default=50,
                     help="timed steps of the other 3D precisions")
     ap.add_argument("--porous-steps", type=int, default=2000)
-    ap.add_argument("--cpu-steps", type=int, default=40)
+    ap.add_argument("--cpu-steps", type=int, default=160)
     ap.add_argument("--err-steps", type=int, default=40,
                     help="steps of the reduced boxes for the error columns")
     ap.add_argument("--samples", type=int, default=12,
