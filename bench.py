@@ -629,9 +629,9 @@ def main():
     ap.add_argument("--leg-steps", type=int, default=50,
                     help="timed steps of the other 3D precisions")
     ap.add_argument("--porous-steps", type=int, default=2000)
-    ap.add_argument("--cpu-steps", type=int, default=160)
-    ap.add_argument("--err-steps", type=int, default=40,
-                    help="steps of the reduced boxes for the error columns")
+    ap.add_argument("--cpu-steps", type=int, default=160,
+                    help="oracle steps on the reduced 3D box (also the "
+                         "steps of the error columns there)")
     ap.add_argument("--samples", type=int, default=12,
                     help="sampled nodes of the full-size one-step check")
     ap.add_argument("--skip-cpu", action="store_true",
