@@ -151,9 +151,9 @@ int ddcc_init_fields_dev(ddcc_ctx* ctx, const double* C_dev,
                          const double* u_dev, const double* P_dev);
 
 /* Advances nsteps >= 0 time steps (eqs. 3.1, 3.2), asynchronously on the
- * context stream: in 2D one fused kernel per step; in 3D two, one forming
- * C_i from the pulled phase populations and one z-marching kernel for the
- * chemical potential and the node update. */
+ * context stream: in 2D one fused kernel per step; in 3D three, one forming
+ * C_i from the pulled phase populations, one z-marching kernel for the
+ * chemical potential mu_i, and one z-marching kernel for the node update. */
 int ddcc_step(ddcc_ctx* ctx, int64_t nsteps);
 
 /* C_i, u and P of the current time level (moment recovery of Section 3 and
