@@ -81,15 +81,21 @@ __device__ inline void collide_phase(const R* fp, R em, const R* X,
   from_hermite<L>(ms, del, cs2);
 }
 
-// Flow set. gp: pulled populations (g_0 stored as g_0 - rho0); J = phi rho
-// u; A, M packed symmetric tensors; a0 = phi u.grad rho; F total force;
-// s21, s22 local rates, sg the others; q4 fourth-order constants.
+// Flow set. gp: pulled populations (g_0 stored as g_0 - rho0); A, M packed
+// symmetric tensors; a0 = phi u.grad rho; F total force; s21, s22 local
+// rates, sg the others; q4 fourth-order constants.
+// First-order rows: the velocity solves phi rho u = j + F/2 with F the total
+// force (penalty included, eq. 3.13), so the first moment of g - g^eq is
+// j - phi rho u = -F/2 exactly and the row's post-collision moment
+// s (j - phi rho u) - (1 - s/2) F is -F for every rate s. The kernels use
+// that value: formed as the difference of j and phi rho u, the rounding of
+// phi rho u (relative to u, not to F) repeats with the same sign every step
+// where the fields are steady, and adds up in float32.
 template <class L, class R>
-__device__ inline void collide_flow(const R* gp, const R* J, const R* A,
-                                    R psiP, const R* M, R a0, const R* F,
-                                    R s21, R s22, const R* sg,
-                                    const R (*q4)[3], R cs2, R inv_cs2,
-                                    R* del) {
+__device__ inline void collide_flow(const R* gp, const R* A, R psiP,
+                                    const R* M, R a0, const R* F, R s21,
+                                    R s22, const R* sg, const R (*q4)[3],
+                                    R cs2, R inv_cs2, R* del) {
   constexpr int Q = L::Q;
   constexpr int D = L::D;
   R r[Q], h[Q], ms[Q];
@@ -99,15 +105,13 @@ __device__ inline void collide_flow(const R* gp, const R* J, const R* A,
     constexpr int k = decltype(kc)::value;
     constexpr int grp = L::rows[k].group;
     R meq, mg, s;
-    if constexpr (grp == GR0) {
+    if constexpr (grp == GR1) {
+      ms[k] = -F[row_comp<L>(k)];  // phi rho u = j + F/2
+      return;
+    } else if constexpr (grp == GR0) {
       meq = R(0);
       mg = a0;
       s = sg[GR0];
-    } else if constexpr (grp == GR1) {
-      constexpr int a = row_comp<L>(k);
-      meq = J[a];
-      mg = F[a];
-      s = sg[GR1];
     } else if constexpr (grp == GR21) {
       constexpr int a = row_comp<L>(k);
       meq = A[sym_diag<D>(a)] + psiP;

@@ -528,10 +528,9 @@ struct Step2D {
                       dtY[1] + k.cs2 * (u[0] * gprho[1] + gprho[0] * u[1]),
                       dtY[2] + R(2) * k.cs2 * u[1] * gprho[1] + k.one_m3cs2 * ub};
       const R a0 = psi * (u[0] * grho[0] + u[1] * grho[1]);
-      const R J[2] = {psirho * u[0], psirho * u[1]};
       R del[Q];
-      collide_flow<D2Q9>(gp, J, A, psiP, M, a0, F, s21, s22, k.sg, k.q4,
-                         k.cs2, k.inv_cs2, del);
+      collide_flow<D2Q9>(gp, A, psiP, M, a0, F, s21, s22, k.sg, k.q4, k.cs2,
+                         k.inv_cs2, del);
 #pragma unroll
       for (int p = 0; p < Q; ++p) stp(b.gB + (long long)(p) * n, idx, Pop(gp[p] - del[p]));
     }

@@ -563,9 +563,8 @@ __device__ inline void step3d_node(const Coef<double>& kd, const Coef<R>& k,
                     dtY[4] + k.cs2 * (u[1] * gprho[2] + gprho[1] * u[2]),
                     dtY[5] + R(2) * k.cs2 * u[2] * gprho[2] + k.one_m3cs2 * ub};
     const R a0 = psi * (u[0] * grho[0] + u[1] * grho[1] + u[2] * grho[2]);
-    const R J[3] = {psirho * u[0], psirho * u[1], psirho * u[2]};
     R del[QG];
-    collide_flow<LG>(gp, J, A, psiP, M, a0, F, s21, s22, k.sg, k.q4, k.cs2,
+    collide_flow<LG>(gp, A, psiP, M, a0, F, s21, s22, k.sg, k.q4, k.cs2,
                      k.inv_cs2, del);
 #pragma unroll
     for (int p = 0; p < QG; ++p) stp(b.gB + (long long)p * n, idx, Pop(gp[p] - del[p]));
