@@ -1,7 +1,7 @@
 """Parity of the HIP path (through the C ABI) with the FP64 oracle.
 
 FP64 bar: relative L-inf <= 1e-10 for C_i, u and P, mass drift <= 1e-12.
-FP32 bar: relative L-inf <= 1e-5 of C_i and u, mass drift <= 1e-6.
+FP32 bar: relative L-inf <= 1e-5 of C_i, u and P, mass drift <= 1e-6.
 """
 import numpy as np
 import pytest
@@ -133,19 +133,23 @@ def test_short_run_fp32(k):
     o = oracle_run(wl, 60)
     g = gpu_run(wl, 60, "fp32")
     e = _report("fp32 60 steps", g, o)
-    assert e["C"] < 1e-5 and e["u"] < 1e-4
+    assert max(e.values()) < 1e-5
     drift = np.abs(g["mass"] - g["mass0"]) / np.abs(g["mass0"])
     assert drift.max() < 1e-6
 
 
 def test_disk_droplet_1000_steps_fp32():
-    """Same case in FP32 storage and arithmetic: C_i and u within 1e-5 of the
-    FP64 oracle after 1000 steps, mass drift below 1e-6."""
+    """Same case in FP32 storage and arithmetic: C_i, u and P (where psi >=
+    1e-2) within 1e-5 of the FP64 oracle after 1000 steps, mass drift below
+    1e-6."""
     wl = W.disk_on_droplet_2d(n=128)
     o = oracle_run(wl, 1000)
     g = gpu_run(wl, 1000, "fp32")
     e = _report("disk 1000 fp32", g, o)
-    assert e["C"] < 1e-5 and e["u"] < 1e-5
+    fl = wl.psi >= 1e-2
+    eP = rel_linf(g["P"][fl], o["P"][fl])
+    print("P(psi>=1e-2) %.2e" % eP, flush=True)
+    assert e["C"] < 1e-5 and e["u"] < 1e-5 and eP < 1e-5
     drift = np.abs(g["mass"] - g["mass0"]) / np.abs(g["mass0"])
     print("fp32 drift", drift, flush=True)
     assert drift.max() < 1e-6
@@ -181,7 +185,7 @@ def test_porous_full_size_one_step(precision, tol):
     assert max(eC, eu, ef, eg) < tol and eP < 100 * tol
 
 
-@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 1e-4)])
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 1e-5)])
 def test_porous_reduced_100_steps(precision, tol):
     """256 x 256 version of the porous workload (same generator, radii scaled
     by 1/2), 100 steps against the oracle."""
@@ -189,7 +193,7 @@ def test_porous_reduced_100_steps(precision, tol):
     o = oracle_run(wl, 100)
     g = gpu_run(wl, 100, precision)
     e = _report("porous256 %s" % precision, g, o)
-    assert e["C"] < tol and e["u"] < tol
+    assert max(e.values()) < tol
 
 
 # ---- several walls with their own angles (Section 4.5) --------------------
@@ -203,6 +207,9 @@ def test_two_wall_channel(precision, tol):
     o = oracle_run(wl, 100)
     g = gpu_run(wl, 100, precision)
     e = _report("two walls %s 100 steps" % precision, g, o)
-    assert e["C"] < tol and e["u"] < tol
+    fl = wl.psi >= 1e-2
+    eP = rel_linf(g["P"][fl], o["P"][fl])
+    print("P(psi>=1e-2) %.2e" % eP, flush=True)
+    assert e["C"] < tol and e["u"] < tol and eP < tol
     drift = np.abs(g["mass"] - g["mass0"]) / np.abs(g["mass0"])
     assert drift.max() < (1e-12 if precision == "fp64" else 1e-6)

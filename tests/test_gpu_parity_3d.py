@@ -82,7 +82,7 @@ def test_short_run_3d_fp32(k):
     g = gpu_run(wl, 30, "fp32")
     e = _err(g, o)
     print("fp32 30 steps", e, flush=True)
-    assert e["C"] < 1e-5 and e["u"] < 1e-4
+    assert max(e.values()) < 1e-5
     drift = np.abs(g["mass"] - g["mass0"]) / np.abs(g["mass0"])
     assert drift.max() < 1e-6
 
@@ -119,7 +119,7 @@ def test_long_run_3d_1000_steps():
                        np.abs(g["mass0"])).max())
         g["sim"].close()
         print("%s 1000 steps" % precision, e, "drift %.1e" % drift, flush=True)
-        assert e["C"] < tol and e["u"] < tol
+        assert max(e.values()) < tol
         assert drift < dtol
 
 
@@ -157,7 +157,7 @@ def test_two_walls_3d(precision, tol):
     assert drift < (1e-12 if precision == "fp64" else 1e-6)
 
 
-@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 1e-4)])
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 1e-5)])
 def test_sphere_droplet_32(precision, tol):
     """32^3 version of the sphere / impacting-droplet case (sizes scaled by
     1/8), 40 steps against the oracle."""
@@ -168,7 +168,7 @@ def test_sphere_droplet_32(precision, tol):
     fl = wl.psi >= 1e-3
     eP = rel_linf(g["P"][fl], o["P"][fl])
     print("sphere32 %s" % precision, e, "P(psi>=1e-3) %.2e" % eP, flush=True)
-    assert e["C"] < tol and e["u"] < tol and eP < 10 * tol
+    assert e["C"] < tol and e["u"] < tol and eP < tol
 
 
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 2e-5)])
@@ -223,13 +223,13 @@ def test_d3q7_one_step_fp64():
     sim.close()
 
 
-@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 1e-4)])
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 1e-5)])
 def test_d3q7_short_run(precision, tol):
     wl = _d3q7_case(22)
     o = oracle_run(wl, 30)
     g = gpu_run(wl, 30, precision)
     e = _err(g, o)
     print("d3q7 %s 30 steps" % precision, e, flush=True)
-    assert e["C"] < tol and e["u"] < tol
+    assert max(e.values()) < tol
     drift = np.abs(g["mass"] - g["mass0"]) / np.abs(g["mass0"])
     assert drift.max() < (1e-12 if precision == "fp64" else 1e-6)
