@@ -483,7 +483,8 @@ int ddcc_create(const ddcc_params* p, void* stream, ddcc_ctx** out) {
   c->Qf = lattice_q(p->lattice_f);
   c->Qg = lattice_q(p->lattice_g);
   const int d = p->dim;
-  c->nhist = p->nphase * d + d * (d + 1) / 2 + 1;
+  // 2D: phi C_i u (2N), Y (3), P; 3D: phi C_i (N), u (3), m^C (3), P
+  c->nhist = d == 2 ? 2 * p->nphase + 4 : p->nphase + 7;
   c->nT = d * (d - 1) / 2;
   c->esz = p->precision == DDCC_FP64 ? 8 : 4;
   c->pesz = p->precision == DDCC_FP64 ? 8 : (p->precision == DDCC_FP32 ? 4 : 2);
@@ -836,7 +837,7 @@ int ddcc_save(ddcc_ctx* c, void* buf, size_t* bytes) {
   }
   if (*bytes < need) return fail(c, DDCC_E_INVAL, "buffer too small");
   SaveHeader h{};
-  std::memcpy(h.magic, "DDCCSAV3", 8);
+  std::memcpy(h.magic, "DDCCSAV4", 8);
   h.dim = c->p.dim;
   h.nx = c->p.nx;
   h.ny = c->p.ny;
@@ -885,7 +886,7 @@ int ddcc_load(ddcc_ctx* c, const void* buf, size_t bytes) {
   if (bytes < need) return fail(c, DDCC_E_INVAL, "checkpoint too small");
   SaveHeader h;
   std::memcpy(&h, buf, sizeof(h));
-  if (std::memcmp(h.magic, "DDCCSAV3", 8) != 0 || h.dim != c->p.dim ||
+  if (std::memcmp(h.magic, "DDCCSAV4", 8) != 0 || h.dim != c->p.dim ||
       h.nx != c->p.nx || h.ny != c->p.ny || h.nz != c->p.nz ||
       h.nphase != c->p.nphase || h.lattice_f != c->p.lattice_f ||
       h.lattice_g != c->p.lattice_g || h.precision != c->p.precision ||

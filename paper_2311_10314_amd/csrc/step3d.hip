@@ -29,8 +29,12 @@
 // latencies are not hidden.)
 //
 // Storage as in 2D: float64 rest populations of the phase sets in their own
-// plane, g_0 stored as g_0 - rho0, history phi C_i u (3N), Y (6), P in place,
-// T (xy, xz, yz) double-buffered. C, mu, psi rho and the chemical potential
+// plane, g_0 stored as g_0 - rho0, T (xy, xz, yz) double-buffered. The
+// history (in place) holds the factors of the lagged terms rather than the
+// products: phi C_i (N), u (3), m^C (3) and P, N + 7 fields instead of the
+// 3N + 7 of phi C_i u, Y and P. The next step forms phi C_i u and
+// Y = sym(phi m^C u) from them with the expressions (and so the roundings)
+// of the step that stored them. C, mu, psi rho and the chemical potential
 // are evaluated in float64 in every precision.
 #include <hip/hip_runtime.h>
 
@@ -92,6 +96,29 @@ __device__ inline T sdiv_psi_grad(const Star<T>& ps, const Star<T>& c) {
     r += T(stencil_w<q>()) * (ps.v[q] + ps.v[0]) * (c.v[q] - c.v[0]);
   });
   return r;
+}
+
+// History fields of the 3D step (in place, field type S): phi C_i (N), u
+// (3), m^C (3), P.
+constexpr int H3_C = 0;
+template <int N>
+constexpr int H3_U = N;
+template <int N>
+constexpr int H3_M = N + 3;
+template <int N>
+constexpr int H3_P = N + 6;
+
+// Y = sym(phi m^C u), packed xx, xy, xz, yy, yz, zz. The step that stores
+// m^C and u and the next one, which forms its Y again from them, evaluate
+// the same expressions.
+template <class R>
+__device__ inline void sym_flux(R psi, const R* m, const R* u, R* Y) {
+  Y[0] = psi * m[0] * u[0];
+  Y[1] = R(0.5) * psi * (m[0] * u[1] + u[0] * m[1]);
+  Y[2] = R(0.5) * psi * (m[0] * u[2] + u[0] * m[2]);
+  Y[3] = psi * m[1] * u[1];
+  Y[4] = R(0.5) * psi * (m[1] * u[2] + u[1] * m[2]);
+  Y[5] = psi * m[2] * u[2];
 }
 
 // Periodic neighbourhood of node (x, y, z).
@@ -213,7 +240,11 @@ __global__ __launch_bounds__(TX* TY) void k_frac3d(Coef<double> k,
 // ring, so each value is fetched once per tile instead of once per
 // neighbour (the 19-point stencil otherwise issues 19 loads per node and
 // field through L2). Loads, sums and their order are those of the gathered
-// form.
+// form. The ring holds the fields in their storage type (float32 in float
+// contexts; 256^3 FP32: 196 -> 185 us per launch against a float64 ring,
+// same box). The step kernel's ring stays float64: typed as the fields it
+// took more registers and was slower (FP32 2.69 -> 2.73 ms, FP16 1.89 ->
+// 2.81 ms per step).
 // Planes per workgroup: each column reloads two halo planes, but more
 // columns run at once (same box, 256^3 per step, 16 -> 8 planes: FP32 2.86 ->
 // 2.80 ms, FP16 and BF16 0.5 % faster, FP64 unchanged; 4 planes: FP32 2.78
@@ -224,9 +255,9 @@ template <int N, class Pop, class S, int TY>
 __global__ __launch_bounds__(TX* TY) void k_mu3d(Coef<double> k, Bufs<Pop, S> b) {
   using D = double;
   constexpr int HX = TX + 2, HY = TY + 2, HN = HX * HY;
-  struct Plane {
-    D c[N][HY][HX];
-    D p[HY][HX];
+  struct Plane {  // in the field type: float64 <- S conversions are exact
+    S c[N][HY][HX];
+    S p[HY][HX];
   };
   __shared__ Plane ring[3];
   const int nx = k.nx, ny = k.ny, nz = k.nz;
@@ -253,10 +284,10 @@ __global__ __launch_bounds__(TX* TY) void k_mu3d(Coef<double> k, Bufs<Pop, S> b)
       const unsigned idx = (unsigned(zw) * unsigned(ny) +
                             unsigned(wrap(y0 + ly - 1, ny))) * unsigned(nx) +
                            unsigned(wrap(x0 + lx - 1, nx));
-      pl.p[ly][lx] = D(ldp(b.psi, idx));
+      pl.p[ly][lx] = ldp(b.psi, idx);
 #pragma unroll
       for (int j = 0; j < N; ++j)
-        pl.c[j][ly][lx] = D(ldp(work_field<S>(b.fC) + (long long)j * k.n, idx));
+        pl.c[j][ly][lx] = ldp(work_field<S>(b.fC) + (long long)j * k.n, idx);
     }
   };
 
@@ -283,8 +314,8 @@ __global__ __launch_bounds__(TX* TY) void k_mu3d(Coef<double> k, Bufs<Pop, S> b)
         D r = D(0);
         static_for<1, 19>([&](auto qc) {
           constexpr int q = decltype(qc)::value;
-          const D pq = at(qc, [](const Plane& pl, int yy, int xx) { return pl.p[yy][xx]; });
-          const D cq = at(qc, [j](const Plane& pl, int yy, int xx) { return pl.c[j][yy][xx]; });
+          const D pq = D(at(qc, [](const Plane& pl, int yy, int xx) { return pl.p[yy][xx]; }));
+          const D cq = D(at(qc, [j](const Plane& pl, int yy, int xx) { return pl.c[j][yy][xx]; }));
           r += D(stencil_w<q>()) * (pq + psi) * (cq - c0);
         });
         L[j] = r;
@@ -467,7 +498,7 @@ __device__ inline void step3d_node(const Coef<double>& kd, const Coef<R>& k,
     const R j[3] = {R(jd[0]), R(jd[1]), R(jd[2])};
     // force (eq. 3.13): -div T^{n-1} + sum_i phi mu_i grad C_i
     //                   + P^{n-1} grad psi + psi (rho a + G)
-    const R Pprev = R(ldp(b.hist + (long long)(3 * N + 6) * n, idx));
+    const R Pprev = R(ldp(b.hist + (long long)(H3_P<N>) * n, idx));
     R Fp[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -486,20 +517,22 @@ __device__ inline void step3d_node(const Coef<double>& kd, const Coef<R>& k,
   }
 
   // Y = sym(phi m^C u): xx, xy, xz, yy, yz, zz; T = antisym: xy, xz, yz
-  const R Y[6] = {psi * mC[0] * u[0],
-                  R(0.5) * psi * (mC[0] * u[1] + u[0] * mC[1]),
-                  R(0.5) * psi * (mC[0] * u[2] + u[0] * mC[2]),
-                  psi * mC[1] * u[1],
-                  R(0.5) * psi * (mC[1] * u[2] + u[1] * mC[2]),
-                  psi * mC[2] * u[2]};
+  R Y[6];
+  sym_flux(psi, mC, u, Y);
   const R Tn[3] = {R(0.5) * psi * (mC[0] * u[1] - u[0] * mC[1]),
                    R(0.5) * psi * (mC[0] * u[2] - u[0] * mC[2]),
                    R(0.5) * psi * (mC[1] * u[2] - u[1] * mC[2])};
   R dtY[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
   if constexpr (MODE != MODE_INIT) {
+    R uprev[3], mprev[3], Yprev[6];
 #pragma unroll
-    for (int q = 0; q < 6; ++q)
-      dtY[q] = Y[q] - R(ldp(b.hist + (long long)(3 * N + q) * n, idx));
+    for (int a = 0; a < 3; ++a) {
+      uprev[a] = R(ldp(b.hist + (long long)(H3_U<N> + a) * n, idx));
+      mprev[a] = R(ldp(b.hist + (long long)(H3_M<N> + a) * n, idx));
+    }
+    sym_flux(psi, mprev, uprev, Yprev);
+#pragma unroll
+    for (int q = 0; q < 6; ++q) dtY[q] = Y[q] - Yprev[q];
   }
   // local flow rates from nu (eq. 16)
   R nu = R(0);
@@ -590,8 +623,7 @@ __device__ inline void step3d_node(const Coef<double>& kd, const Coef<R>& k,
       // the storage rounding of the moving populations
       stp(b.f0B + (long long)i * n, idx,
           (kd.wf[0] - D(1)) * kd.eta[i] * psimu_d[i] + psiC + comp);
-#pragma unroll
-      for (int a = 0; a < 3; ++a) stp(b.hist + (long long)(3 * i + a) * n, idx, S(X[a]));
+      stp(b.hist + (long long)(H3_C + i) * n, idx, S(R(psiC)));
     } else {
       // own phi C_i = sum of the pulled populations (Section 3): moving
       // populations summed in the storage precision, the float64 rest
@@ -607,6 +639,13 @@ __device__ inline void step3d_node(const Coef<double>& kd, const Coef<R>& k,
       });
       const D f0 = ldp(b.f0A + (long long)i * n, idx);
       const R psiC = R(f0 + D(mv));
+      // phi C_i u of the previous step from its stored factors (phi C_i is
+      // read before this step overwrites it)
+      const R psiCprev = R(ldp(b.hist + (long long)(H3_C + i) * n, idx));
+      R Xprev[3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+        Xprev[a] = psiCprev * R(ldp(b.hist + (long long)(H3_U<N> + a) * n, idx));
       const R X[3] = {psiC * u[0], psiC * u[1], psiC * u[2]};
       // S_i (eq. 3.7) and V = d_t(phi C_i u) + c_s^2 eta (mu grad psi - S_i)
       R V[3];
@@ -616,7 +655,7 @@ __device__ inline void step3d_node(const Coef<double>& kd, const Coef<R>& k,
 #pragma unroll
         for (int j = 0; j < N; ++j)
           if (j != i) sa -= C[i] * C[j] * gmu[j][a];
-        const R dX = X[a] - R(ldp(b.hist + (long long)(3 * i + a) * n, idx));
+        const R dX = X[a] - Xprev[a];
         V[a] = dX + k.cs2 * k.eta[i] * (mu[i] * gpsi[a] - psi * sa);
       }
       R del[QF];
@@ -627,13 +666,15 @@ __device__ inline void step3d_node(const Coef<double>& kd, const Coef<R>& k,
         stp(phase_plane(b.fB, i, p, QF, n), idx,
             narrow<Pop>(fp[p] - del[p], comp));
       stp(b.f0B + (long long)i * n, idx, f0 - D(del[0]) + comp);
-#pragma unroll
-      for (int a = 0; a < 3; ++a) stp(b.hist + (long long)(3 * i + a) * n, idx, S(X[a]));
+      stp(b.hist + (long long)(H3_C + i) * n, idx, S(psiC));
     }
   }
 #pragma unroll
-  for (int q = 0; q < 6; ++q) stp(b.hist + (long long)(3 * N + q) * n, idx, S(Y[q]));
-  stp(b.hist + (long long)(3 * N + 6) * n, idx, S(P));
+  for (int a = 0; a < 3; ++a) {
+    stp(b.hist + (long long)(H3_U<N> + a) * n, idx, S(u[a]));
+    stp(b.hist + (long long)(H3_M<N> + a) * n, idx, S(mC[a]));
+  }
+  stp(b.hist + (long long)(H3_P<N>) * n, idx, S(P));
 #pragma unroll
   for (int c = 0; c < 3; ++c) stp(b.TB + (long long)c * n, idx, S(Tn[c]));
 }

@@ -41,7 +41,11 @@ def unpack_state(sim, buf, lazy=False):
     Qf, Qg = qs[lf], qs[lg]
     shape = (ny, nx) if dim == 2 else (nz, ny, nx)
     n = nx * ny * nz
-    nhist = N * dim + dim * (dim + 1) // 2 + 1
+    magic = bytes(hdr[:8])
+    # history: phi C_i u (N d), Y (d(d+1)/2), P; from DDCCSAV4 on the 3D
+    # step keeps the factors phi C_i (N), u (3), m^C (3), P instead
+    factors = magic >= b"DDCCSAV4" and dim == 3
+    nhist = N + 7 if factors else N * dim + dim * (dim + 1) // 2 + 1
     nT = dim * (dim - 1) // 2
     fdt = np.float64 if prec == FP64 else np.float32      # fields
     pdt = {FP64: np.float64, FP32: np.float32, FP16: np.float16,
@@ -50,7 +54,7 @@ def unpack_state(sim, buf, lazy=False):
     raw = memoryview(buf)[56:]
     # DDCCSAV2 kept an unused plane 0 in each phase set's moving block;
     # DDCCSAV3 stores only the moving planes p >= 1
-    skip = bytes(hdr[:8]) == b"DDCCSAV2"
+    skip = magic == b"DDCCSAV2"
 
     def conv(a):
         a = np.asarray(a)
@@ -74,7 +78,7 @@ def unpack_state(sim, buf, lazy=False):
     hist = data[:nhist * n].reshape((nhist,) + shape)
     T = data[nhist * n:(nhist + nT) * n].reshape((nT,) + shape)
     out = dict(g=g, hist=hist, T=T, t=t, dim=dim, N=N, lf=lf, lg=lg,
-               pops=conv)
+               pops=conv, hist_factors=factors)
     if lazy:
         out.update(fmov=fview, f0=f0)
         return out
@@ -140,21 +144,37 @@ def gpu_state_to_oracle(wl, sim):
     g[0] += wl.params["rho0"]
     h = np.asarray(s["hist"], np.float64)
     shape = wl.shape
-    X = h[:N * d].reshape((N, d) + shape)
-    Y = np.zeros((d, d) + shape)
+    X, Y, P = history_to_oracle(h, N, d, np.asarray(wl.psi, np.float64),
+                                s["hist_factors"])
     T = np.zeros((d, d) + shape)
-    o = N * d
-    pairs = [(a, b) for a in range(d) for b in range(a, d)]
-    for k, (a, b) in enumerate(pairs):
-        Y[a, b] = h[o + k]
-        Y[b, a] = h[o + k]
-    P = h[o + len(pairs)].copy()
     tpairs = [(a, b) for a in range(d) for b in range(a + 1, d)]
     Tg = np.asarray(s["T"], np.float64)
     for k, (a, b) in enumerate(tpairs):
         T[a, b] = Tg[k]
         T[b, a] = -Tg[k]
     return State(f, g, X, Y, P, T)
+
+
+def history_to_oracle(h, N, d, psi, factors):
+    """X = phi C_i u (N, d, grid), Y (d, d, grid) and P of the oracle State
+    from a checkpoint's history h (float64 (nhist, grid)); psi on the same
+    grid (the factors form of the 3D step stores phi C_i, u, m^C and P, and
+    Y = psi sym(m^C u))."""
+    shape = h.shape[1:]
+    pairs = [(a, b) for a in range(d) for b in range(a, d)]
+    Y = np.zeros((d, d) + shape)
+    if factors:
+        psiC, u, m, P = h[:N], h[N:N + d], h[N + d:N + 2 * d], h[N + 2 * d]
+        X = psiC[:, None] * u[None]
+        for a, b in pairs:
+            Y[a, b] = Y[b, a] = psi * 0.5 * (m[a] * u[b] + u[a] * m[b])
+        return X, Y, P.copy()
+    X = h[:N * d].reshape((N, d) + shape)
+    o = N * d
+    for k, (a, b) in enumerate(pairs):
+        Y[a, b] = h[o + k]
+        Y[b, a] = h[o + k]
+    return X, Y, h[o + len(pairs)].copy()
 
 
 def window_state(wl, s, center, hw):
@@ -184,15 +204,9 @@ def window_state(wl, s, center, hw):
     g[0] += wl.params["rho0"]
     h = np.asarray(sub(s["hist"]), np.float64)[crop]
     wshape = h.shape[1:]
-    X = h[:N * d].reshape((N, d) + wshape)
-    Y = np.zeros((d, d) + wshape)
+    psiw = np.asarray(sub(np.asarray(wl.psi, np.float64)))[crop]
+    X, Y, P = history_to_oracle(h, N, d, psiw, s["hist_factors"])
     T = np.zeros((d, d) + wshape)
-    o = N * d
-    pairs = [(a, b) for a in range(d) for b in range(a, d)]
-    for k, (a, b) in enumerate(pairs):
-        Y[a, b] = h[o + k]
-        Y[b, a] = h[o + k]
-    P = h[o + len(pairs)].copy()
     tpairs = [(a, b) for a in range(d) for b in range(a + 1, d)]
     Tg = np.asarray(sub(s["T"]), np.float64)[crop]
     for k, (a, b) in enumerate(tpairs):
