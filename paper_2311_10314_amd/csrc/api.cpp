@@ -20,6 +20,19 @@ namespace {
 
 const char* kVersion = "ddcc 0.1 (gfx950)";
 
+// Memory-side (Infinity) cache of the chip. A step that moves more than
+// this streams its outputs (MODE_STREAM): 256^3 3D and 2048^2 2D steps 3-6 %
+// faster; on a 512^2 box, whose step stays in this cache, plain stores are
+// 19 % faster.
+constexpr size_t kCacheBytes = size_t(256) << 20;
+
+// Bytes one step moves: the populations (one buffer read, the other
+// written), T likewise, the in-place history read and written, and the 3D
+// work fields written and read.
+size_t step_bytes(size_t pops, size_t T, size_t hist, size_t work) {
+  return 2 * (pops + T + hist + work);
+}
+
 int fail(ddcc_ctx* c, int code, const std::string& msg) {
   if (c) c->err = msg;
   return code;
@@ -318,6 +331,7 @@ hipError_t launch_as(ddcc_ctx* c, const Coef<R>& k, int mode,
                      const double* inC, const double* inU, const double* inP,
                      double* oC, double* oU, double* oP) {
   Bufs<Pop, S> b = bufs<Pop, S>(c, mode);
+  if (mode == MODE_STEP && c->stream_stores) mode = MODE_STREAM;
   b.inC = inC;
   b.inU = inU;
   b.inP = inP;
@@ -521,6 +535,10 @@ int ddcc_create(const ddcc_params* p, void* stream, ddcc_ctx** out) {
     if (e == hipSuccess) e = hipMalloc(&c->T[a], sT);
   }
   if (e == hipSuccess) e = hipMalloc(&c->hist, (size_t)c->nhist * n * c->esz);
+  c->stream_stores =
+      step_bytes(sf + sg + (size_t)p->nphase * n * sizeof(double), sT,
+                 (size_t)c->nhist * n * c->esz,
+                 d == 3 ? (size_t)2 * p->nphase * n * c->esz : 0) > kCacheBytes;
   if (e == hipSuccess) e = hipMalloc(&c->psi, n * c->esz);
   if (e == hipSuccess)
     e = hipMalloc(&c->wet, (size_t)(p->nphase - 1) * n * c->esz);
@@ -1114,6 +1132,7 @@ struct ddcc_batch {
   int ty = 8;
   int blocks = 1;                // persistent workgroups per launch
   int graph_steps = 0;           // 0: one launch per step, no graph
+  bool stream_stores = false;    // steps as MODE_STREAM (see ddcc_ctx)
   hipGraphExec_t gexec[2] = {nullptr, nullptr};  // by parity of cur
   int cur = 0;
   int cus = 0;
@@ -1236,6 +1255,7 @@ hipError_t batch_launch_as(ddcc_batch* b, const Coef<R>* k, int mode,
                            const double* inP, double* oC, double* oU,
                            double* oP) {
   Bufs<Pop, S> r = batch_bufs<Pop, S>(b, mode);
+  if (mode == MODE_STEP && b->stream_stores) mode = MODE_STREAM;
   r.inC = inC;
   r.inU = inU;
   r.inP = inP;
@@ -1419,6 +1439,10 @@ int ddcc_batch_create(const ddcc_params* p, int count, const int* nx,
     if (e == hipSuccess) e = hipMalloc(&b->T[a], nt * b->esz);
   }
   if (e == hipSuccess) e = hipMalloc(&b->hist, (size_t)nhist_of(N) * nt * b->esz);
+  b->stream_stores =
+      step_bytes((size_t)N * (kBatchQ - 1) * nt * b->pesz +
+                     (size_t)N * nt * sizeof(double) + (size_t)kBatchQ * nt * b->pesz,
+                 nt * b->esz, (size_t)nhist_of(N) * nt * b->esz, 0) > kCacheBytes;
   if (e == hipSuccess) e = hipMalloc(&b->psi, nt * b->esz);
   if (e == hipSuccess) e = hipMalloc(&b->wet, (size_t)(N - 1) * nt * b->esz);
   if (e == hipSuccess)

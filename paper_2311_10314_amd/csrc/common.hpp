@@ -39,9 +39,23 @@ __host__ __device__ inline T* phase_plane(T* f, int i, int p, int Q,
   return f + ((long long)i * (Q - 1) + (p - 1)) * n;
 }
 
-template <class T>
+// Store of element i of a plane. NT: a nontemporal (streaming) store, for
+// the outputs of a step whose working set is larger than the memory-side
+// cache; they are read again only by the next step, after the whole grid
+// has gone through the caches.
+template <bool NT = false, class T>
 __device__ inline void stp(T* plane, unsigned i, T v) {
-  *reinterpret_cast<T*>(reinterpret_cast<char*>(plane) + i * unsigned(sizeof(T))) = v;
+  T* q = reinterpret_cast<T*>(reinterpret_cast<char*>(plane) +
+                              i * unsigned(sizeof(T)));
+  if constexpr (NT && sizeof(T) == 2) {
+    unsigned short u;
+    __builtin_memcpy(&u, &v, 2);
+    __builtin_nontemporal_store(u, reinterpret_cast<unsigned short*>(q));
+  } else if constexpr (NT) {
+    __builtin_nontemporal_store(v, q);
+  } else {
+    *q = v;
+  }
 }
 
 }  // namespace ddcc

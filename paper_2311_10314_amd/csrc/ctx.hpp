@@ -41,6 +41,9 @@ struct ddcc_ctx {
   int nwalls = 0;  // walls of the current geometry
   int64_t t = 0;
   int tile_x = 64, tile_y = 8;
+  // steps run as MODE_STREAM (nontemporal stores): what one step moves does
+  // not fit the memory-side cache
+  bool stream_stores = false;
   // periodic in-stream diagnostics (ddcc_set_diagnostics)
   int diag_every = 0;
   int64_t diag_t = -1;          // time level of the last check

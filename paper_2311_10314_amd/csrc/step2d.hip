@@ -123,6 +123,7 @@ __device__ inline Nbr make_nbr(int gx, int gy, int nx, int ny, unsigned off) {
 
 template <int N, class Pop, class S, class R, int MODE, int TY>
 struct Step2D {
+  static constexpr bool STREAM = MODE == MODE_STREAM;  // nontemporal stores
   using D = double;
   static constexpr int Q = 9;
   static constexpr int NT = TX * TY;
@@ -309,7 +310,7 @@ struct Step2D {
     // whole chunk's phase-1 traffic has gone through L2). In float64 that
     // takes the kernel to 187 VGPRs and two waves per SIMD, and is still
     // faster (same box, 512^2 N = 3: 48.3 -> 42.4 us; 2048^2: 825 -> 815 us).
-    constexpr bool KEEP = MODE == MODE_STEP;
+    constexpr bool KEEP = MODE == MODE_STEP || MODE == MODE_STREAM;
     Keep fown;
     node1<KEEP>(sm, kd, b, kd, x0, y0, tx + 2, ty + 2, psiC, &fown);
     for (int r = tid; r < RING1; r += NT) {
@@ -342,7 +343,7 @@ struct Step2D {
     D psiC[N], psimu_d[N], dummy[N];
     // pulled populations kept in registers as in run() (float64, 256
     // instances, 64 x 8 tiles: 0.829 -> 0.756 ms per step, same box)
-    constexpr bool KEEP = MODE == MODE_STEP;
+    constexpr bool KEEP = MODE == MODE_STEP || MODE == MODE_STREAM;
     Keep fown;
     node1<KEEP>(sm, kd, b, gd, x0, y0, tx + 2, ty + 2, psiC, &fown);
     for (int r = tid; r < RING1; r += NT) {
@@ -499,10 +500,10 @@ struct Step2D {
 
     if constexpr (MODE == MODE_MOMENTS) {
 #pragma unroll
-      for (int i = 0; i < N; ++i) stp(b.outC + (long long)(i) * n, idx, double(C[i]));
-      stp(b.outU, idx, double(u[0]));
-      stp(b.outU + n, idx, double(u[1]));
-      stp(b.outP, idx, double(P));
+      for (int i = 0; i < N; ++i) stp<STREAM>(b.outC + (long long)(i) * n, idx, double(C[i]));
+      stp<STREAM>(b.outU, idx, double(u[0]));
+      stp<STREAM>(b.outU + n, idx, double(u[1]));
+      stp<STREAM>(b.outP, idx, double(P));
       return;
     }
 
@@ -519,7 +520,7 @@ struct Step2D {
         if (p == 0) geq -= psiP * k.inv_cs2;  // stored as g_0 - rho0
         // the buffers hold pre-streaming values: place g_p(x) where the
         // next pull reads it, at x - c_p
-        stp(b.gB + (long long)(p) * n, nb.src(cx, cy), Pop(geq));
+        stp<STREAM>(b.gB + (long long)(p) * n, nb.src(cx, cy), Pop(geq));
       }
     } else {
       const R ub = u[0] * gprho[0] + u[1] * gprho[1];
@@ -532,7 +533,7 @@ struct Step2D {
       collide_flow<D2Q9>(gp, A, psiP, M, a0, F, s21, s22, k.sg, k.q4, k.cs2,
                          k.inv_cs2, del);
 #pragma unroll
-      for (int p = 0; p < Q; ++p) stp(b.gB + (long long)(p) * n, idx, Pop(gp[p] - del[p]));
+      for (int p = 0; p < Q; ++p) stp<STREAM>(b.gB + (long long)(p) * n, idx, Pop(gp[p] - del[p]));
     }
 
     // ---- phase sets: equilibrium (3.5), source (3.6, 3.7), collision ---
@@ -546,11 +547,11 @@ struct Step2D {
         for (int p = 1; p < Q; ++p) {
           const int cx = D2Q9::c[p].x, cy = D2Q9::c[p].y;
           const R feq = k.wf[p] * (em + (R(cx) * X[0] + R(cy) * X[1]) * k.inv_cs2);
-          stp(phase_plane(b.fB, i, p, Q, n), nb.src(cx, cy), narrow<Pop>(feq, comp));
+          stp<STREAM>(phase_plane(b.fB, i, p, Q, n), nb.src(cx, cy), narrow<Pop>(feq, comp));
         }
         // f^eq_0 = (w_0 - 1) eta phi mu + phi C (float64 rest plane), plus
         // the storage rounding of the moving populations
-        stp(b.f0B + (long long)(i) * n, idx,
+        stp<STREAM>(b.f0B + (long long)(i) * n, idx,
             (kd.wf[0] - D(1)) * kd.eta[i] * psimu_d[i] + psiC[i] + comp);
       } else {
         // S_i = psi [(C_i sum_{j!=i} C_j - 1) grad mu_i
@@ -583,18 +584,18 @@ struct Step2D {
         D comp = D(0);
 #pragma unroll
         for (int p = 1; p < Q; ++p)
-          stp(phase_plane(b.fB, i, p, Q, n), idx,
+          stp<STREAM>(phase_plane(b.fB, i, p, Q, n), idx,
               narrow<Pop>(fp[p] - del[p], comp));
-        stp(b.f0B + (long long)(i) * n, idx,
+        stp<STREAM>(b.f0B + (long long)(i) * n, idx,
             ldp(b.f0A + (long long)(i) * n, idx) - D(del[0]) + comp);
       }
-      stp(b.hist + (long long)(2 * i) * n, idx, S(X[0]));
-      stp(b.hist + (long long)(2 * i + 1) * n, idx, S(X[1]));
+      stp<STREAM>(b.hist + (long long)(2 * i) * n, idx, S(X[0]));
+      stp<STREAM>(b.hist + (long long)(2 * i + 1) * n, idx, S(X[1]));
     }
 #pragma unroll
-    for (int q = 0; q < 3; ++q) stp(b.hist + (long long)(2 * N + q) * n, idx, S(Y[q]));
-    stp(b.hist + (long long)(2 * N + 3) * n, idx, S(P));
-    stp(b.TB, idx, S(Tn));
+    for (int q = 0; q < 3; ++q) stp<STREAM>(b.hist + (long long)(2 * N + q) * n, idx, S(Y[q]));
+    stp<STREAM>(b.hist + (long long)(2 * N + 3) * n, idx, S(P));
+    stp<STREAM>(b.TB, idx, S(Tn));
   }
 };
 
@@ -651,6 +652,8 @@ hipError_t launch_mode(int mode, const Coef<double>& kd, const Coef<R>& k,
   switch (mode) {
     case MODE_STEP:
       return launch_ty<N, Pop, S, R, MODE_STEP>(kd, k, b, ty, st);
+    case MODE_STREAM:
+      return launch_ty<N, Pop, S, R, MODE_STREAM>(kd, k, b, ty, st);
     case MODE_INIT:
       return launch_ty<N, Pop, S, R, MODE_INIT>(kd, k, b, ty, st);
     default:
@@ -700,6 +703,9 @@ hipError_t launch_batch_n(int mode, const Coef<double>* kd, const Coef<R>* k,
                        st, kd, k, b, tiles, insts, ntiles, counter);
   else if (mode == MODE_MOMENTS)
     hipLaunchKernelGGL((k_step2d_batch<N, Pop, S, R, MODE_MOMENTS, TY>), g, blk,
+                       0, st, kd, k, b, tiles, insts, ntiles, counter);
+  else if (mode == MODE_STREAM)
+    hipLaunchKernelGGL((k_step2d_batch<N, Pop, S, R, MODE_STREAM, TY>), g, blk,
                        0, st, kd, k, b, tiles, insts, ntiles, counter);
   else
     hipLaunchKernelGGL((k_step2d_batch<N, Pop, S, R, MODE_STEP, TY>), g, blk, 0,

@@ -231,7 +231,7 @@ __global__ __launch_bounds__(TX* TY) void k_frac3d(Coef<double> k,
   const D inv = D(1) / (tot > k.psi_min ? tot : k.psi_min);
 #pragma unroll
   for (int i = 0; i < N; ++i)
-    stp(work_field<S>(b.fC) + (long long)i * k.n, idx, S(psiC[i] * inv));
+    stp<MODE == MODE_STREAM>(work_field<S>(b.fC) + (long long)i * k.n, idx, S(psiC[i] * inv));
 }
 
 // ---- k_mu3d ---------------------------------------------------------------
@@ -251,7 +251,7 @@ __global__ __launch_bounds__(TX* TY) void k_frac3d(Coef<double> k,
 // ms, the others 1 % slower than at 16; 32 planes slower for all).
 constexpr int ZB = 8;
 
-template <int N, class Pop, class S, int TY>
+template <int N, class Pop, class S, int TY, bool NT>
 __global__ __launch_bounds__(TX* TY) void k_mu3d(Coef<double> k, Bufs<Pop, S> b) {
   using D = double;
   constexpr int HX = TX + 2, HY = TY + 2, HN = HX * HY;
@@ -351,7 +351,7 @@ __global__ __launch_bounds__(TX* TY) void k_mu3d(Coef<double> k, Bufs<Pop, S> b)
             grad += k.grad34[i][j] * L[j];
             wet += k.wet3[i][j] * W[j];
           }
-        stp(work_field<S>(b.fmu) + (long long)i * k.n, idx,
+        stp<NT>(work_field<S>(b.fmu) + (long long)i * k.n, idx,
             S((psi * bulk + grad + wet) / psih));
       }
     }
@@ -394,6 +394,7 @@ __device__ inline void step3d_node(const Coef<double>& kd, const Coef<R>& k,
   using D = double;
   using Pl = StepPlane<N, TY>;
   constexpr int QF = LF::Q, QG = LG::Q;
+  constexpr bool NT = MODE == MODE_STREAM;  // streaming stores
   const Nbr3 nb = make_nbr3(x, y, z, k.nx, k.ny, k.nz);
   const unsigned idx = nb.at(0, 0, 0);
   const long long n = k.n;
@@ -560,10 +561,10 @@ __device__ inline void step3d_node(const Coef<double>& kd, const Coef<R>& k,
   }
   if constexpr (MODE == MODE_MOMENTS) {
 #pragma unroll
-    for (int i = 0; i < N; ++i) stp(b.outC + i * n, idx, double(C[i]));
+    for (int i = 0; i < N; ++i) stp<NT>(b.outC + i * n, idx, double(C[i]));
 #pragma unroll
-    for (int a = 0; a < 3; ++a) stp(b.outU + a * n, idx, double(u[a]));
-    stp(b.outP, idx, double(P));
+    for (int a = 0; a < 3; ++a) stp<NT>(b.outU + a * n, idx, double(u[a]));
+    stp<NT>(b.outP, idx, double(P));
     return;
   }
 
@@ -584,7 +585,7 @@ __device__ inline void step3d_node(const Coef<double>& kd, const Coef<R>& k,
       if constexpr (p == 0) geq -= psiP * k.inv_cs2;  // stored as g_0 - rho0
       // the buffers hold pre-streaming values: place g_p(x) where the
       // next pull reads it, at x - c_p
-      stp(b.gB + (long long)p * n, nb.src(cx, cy, cz), Pop(geq));
+      stp<NT>(b.gB + (long long)p * n, nb.src(cx, cy, cz), Pop(geq));
     });
   } else {
     const R ub = u[0] * gprho[0] + u[1] * gprho[1] + u[2] * gprho[2];
@@ -600,7 +601,7 @@ __device__ inline void step3d_node(const Coef<double>& kd, const Coef<R>& k,
     collide_flow<LG>(gp, A, psiP, M, a0, F, s21, s22, k.sg, k.q4, k.cs2,
                      k.inv_cs2, del);
 #pragma unroll
-    for (int p = 0; p < QG; ++p) stp(b.gB + (long long)p * n, idx, Pop(gp[p] - del[p]));
+    for (int p = 0; p < QG; ++p) stp<NT>(b.gB + (long long)p * n, idx, Pop(gp[p] - del[p]));
   }
 
   // ---- phase sets: equilibrium (3.5), source (3.6, 3.7), collision ---
@@ -616,14 +617,14 @@ __device__ inline void step3d_node(const Coef<double>& kd, const Coef<R>& k,
         constexpr int cx = LF::c[p].x, cy = LF::c[p].y, cz = LF::c[p].z;
         const R feq = k.wf[p] * (em + (R(cx) * X[0] + R(cy) * X[1] +
                                        R(cz) * X[2]) * k.inv_cs2);
-        stp(phase_plane(b.fB, i, p, QF, n), nb.src(cx, cy, cz),
+        stp<NT>(phase_plane(b.fB, i, p, QF, n), nb.src(cx, cy, cz),
             narrow<Pop>(feq, comp));
       });
       // f^eq_0 = (w_0 - 1) eta phi mu + phi C (float64 rest plane), plus
       // the storage rounding of the moving populations
-      stp(b.f0B + (long long)i * n, idx,
+      stp<NT>(b.f0B + (long long)i * n, idx,
           (kd.wf[0] - D(1)) * kd.eta[i] * psimu_d[i] + psiC + comp);
-      stp(b.hist + (long long)(H3_C + i) * n, idx, S(R(psiC)));
+      stp<NT>(b.hist + (long long)(H3_C + i) * n, idx, S(R(psiC)));
     } else {
       // own phi C_i = sum of the pulled populations (Section 3): moving
       // populations summed in the storage precision, the float64 rest
@@ -663,20 +664,20 @@ __device__ inline void step3d_node(const Coef<double>& kd, const Coef<R>& k,
       D comp = D(0);
 #pragma unroll
       for (int p = 1; p < QF; ++p)
-        stp(phase_plane(b.fB, i, p, QF, n), idx,
+        stp<NT>(phase_plane(b.fB, i, p, QF, n), idx,
             narrow<Pop>(fp[p] - del[p], comp));
-      stp(b.f0B + (long long)i * n, idx, f0 - D(del[0]) + comp);
-      stp(b.hist + (long long)(H3_C + i) * n, idx, S(psiC));
+      stp<NT>(b.f0B + (long long)i * n, idx, f0 - D(del[0]) + comp);
+      stp<NT>(b.hist + (long long)(H3_C + i) * n, idx, S(psiC));
     }
   }
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    stp(b.hist + (long long)(H3_U<N> + a) * n, idx, S(u[a]));
-    stp(b.hist + (long long)(H3_M<N> + a) * n, idx, S(mC[a]));
+    stp<NT>(b.hist + (long long)(H3_U<N> + a) * n, idx, S(u[a]));
+    stp<NT>(b.hist + (long long)(H3_M<N> + a) * n, idx, S(mC[a]));
   }
-  stp(b.hist + (long long)(H3_P<N>) * n, idx, S(P));
+  stp<NT>(b.hist + (long long)(H3_P<N>) * n, idx, S(P));
 #pragma unroll
-  for (int c = 0; c < 3; ++c) stp(b.TB + (long long)c * n, idx, S(Tn[c]));
+  for (int c = 0; c < 3; ++c) stp<NT>(b.TB + (long long)c * n, idx, S(Tn[c]));
 }
 
 // Waves per SIMD the register allocation aims at: what the LDS ring allows
@@ -771,7 +772,8 @@ hipError_t launch_3(const Coef<double>& kd, const Coef<R>& k,
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const dim3 gm(g.x, g.y, (k.nz + ZB - 1) / ZB);
-  hipLaunchKernelGGL((k_mu3d<N, Pop, S, TY>), gm, blk, 0, st, kd, b);
+  hipLaunchKernelGGL((k_mu3d<N, Pop, S, TY, MODE == MODE_STREAM>), gm, blk, 0,
+                     st, kd, b);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (!b.coef_d || !b.coef_r) return hipErrorInvalidValue;
@@ -799,6 +801,8 @@ hipError_t launch_mode3(int mode, int lattice_f, const Coef<double>& kd,
   switch (mode) {
     case MODE_STEP:
       return launch_ty3<N, Pop, S, R, MODE_STEP>(lattice_f, kd, k, b, ty, st);
+    case MODE_STREAM:
+      return launch_ty3<N, Pop, S, R, MODE_STREAM>(lattice_f, kd, k, b, ty, st);
     case MODE_INIT:
       return launch_ty3<N, Pop, S, R, MODE_INIT>(lattice_f, kd, k, b, ty, st);
     default:
