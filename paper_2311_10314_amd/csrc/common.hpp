@@ -30,6 +30,19 @@ __device__ inline T ldp(const T* plane, unsigned i) {
                                      i * unsigned(sizeof(T)));
 }
 
+// Load of a value that no other node reads (the node's own history and rest
+// populations): with NT a nontemporal load, which leaves the caches to the
+// rows that neighbouring nodes share (in streaming steps: 256^3 3D about
+// 1 %, 2048^2 2D 1-2 % faster). Nontemporal loads of the shared rows too
+// cost 15-35 %.
+template <bool NT, class T>
+__device__ inline T ldo(const T* plane, unsigned i) {
+  if constexpr (NT && sizeof(T) >= 4)
+    return __builtin_nontemporal_load(reinterpret_cast<const T*>(
+        reinterpret_cast<const char*>(plane) + i * unsigned(sizeof(T))));
+  return ldp(plane, i);
+}
+
 // Plane of the moving population p >= 1 of phase set i: the phase sets keep
 // only their Q - 1 moving planes, [N][Q-1][n]; their rest populations live
 // in the float64 plane f0.

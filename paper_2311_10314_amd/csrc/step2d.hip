@@ -443,7 +443,7 @@ struct Step2D {
       // force (eq. 3.13): -div T^{n-1} + sum_i phi mu_i grad C_i
       //                   + P^{n-1} grad psi + psi (rho a + G)
       const Patch<R> tp = patch(sm.T, mx, my);
-      const R Pprev = R(ldp(b.hist + (long long)(2 * N + 3) * n, idx));
+      const R Pprev = R(ldo<STREAM>(b.hist + (long long)(2 * N + 3) * n, idx));
       R Fp[2];
       Fp[0] = grad_y(tp) + Pprev * gpsi[0] + psirho * k.accel[0] +
               psi * k.force[0];
@@ -472,7 +472,7 @@ struct Step2D {
     if constexpr (MODE != MODE_INIT) {
 #pragma unroll
       for (int q = 0; q < 3; ++q)
-        dtY[q] = Y[q] - R(ldp(b.hist + (long long)(2 * N + q) * n, idx));
+        dtY[q] = Y[q] - R(ldo<STREAM>(b.hist + (long long)(2 * N + q) * n, idx));
     }
 
     // local flow rates from nu (eq. 16)
@@ -566,8 +566,8 @@ struct Step2D {
           }
         Sx *= psi;
         Sy *= psi;
-        const R dX0 = X[0] - R(ldp(b.hist + (long long)(2 * i) * n, idx));
-        const R dX1 = X[1] - R(ldp(b.hist + (long long)(2 * i + 1) * n, idx));
+        const R dX0 = X[0] - R(ldo<STREAM>(b.hist + (long long)(2 * i) * n, idx));
+        const R dX1 = X[1] - R(ldo<STREAM>(b.hist + (long long)(2 * i + 1) * n, idx));
         const R V[2] = {dX0 + k.cs2 * k.eta[i] * (mu[i] * gpsi[0] - Sx),
                         dX1 + k.cs2 * k.eta[i] * (mu[i] * gpsi[1] - Sy)};
         R fp[Q];

@@ -221,7 +221,7 @@ __global__ __launch_bounds__(TX* TY) void k_frac3d(Coef<double> k,
         mv += R(ldp(phase_plane(b.fA, i, p, QF, k.n),
                     nb.src(LF::c[p].x, LF::c[p].y, LF::c[p].z)));
       });
-      psiC[i] = ldp(b.f0A + (long long)i * k.n, idx) + D(mv);
+      psiC[i] = ldo<MODE == MODE_STREAM>(b.f0A + (long long)i * k.n, idx) + D(mv);
     }
   }
   // C_i = phi C_i / sum_j phi C_j (keeps sum_j C_j = 1 exact)
@@ -499,7 +499,7 @@ __device__ inline void step3d_node(const Coef<double>& kd, const Coef<R>& k,
     const R j[3] = {R(jd[0]), R(jd[1]), R(jd[2])};
     // force (eq. 3.13): -div T^{n-1} + sum_i phi mu_i grad C_i
     //                   + P^{n-1} grad psi + psi (rho a + G)
-    const R Pprev = R(ldp(b.hist + (long long)(H3_P<N>) * n, idx));
+    const R Pprev = R(ldo<NT>(b.hist + (long long)(H3_P<N>) * n, idx));
     R Fp[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -529,7 +529,7 @@ __device__ inline void step3d_node(const Coef<double>& kd, const Coef<R>& k,
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       uprev[a] = R(ldp(b.hist + (long long)(H3_U<N> + a) * n, idx));
-      mprev[a] = R(ldp(b.hist + (long long)(H3_M<N> + a) * n, idx));
+      mprev[a] = R(ldo<NT>(b.hist + (long long)(H3_M<N> + a) * n, idx));
     }
     sym_flux(psi, mprev, uprev, Yprev);
 #pragma unroll
@@ -638,11 +638,11 @@ __device__ inline void step3d_node(const Coef<double>& kd, const Coef<R>& k,
                       nb.src(LF::c[p].x, LF::c[p].y, LF::c[p].z)));
         mv += fp[p];
       });
-      const D f0 = ldp(b.f0A + (long long)i * n, idx);
+      const D f0 = ldo<NT>(b.f0A + (long long)i * n, idx);
       const R psiC = R(f0 + D(mv));
       // phi C_i u of the previous step from its stored factors (phi C_i is
       // read before this step overwrites it)
-      const R psiCprev = R(ldp(b.hist + (long long)(H3_C + i) * n, idx));
+      const R psiCprev = R(ldo<NT>(b.hist + (long long)(H3_C + i) * n, idx));
       R Xprev[3];
 #pragma unroll
       for (int a = 0; a < 3; ++a)
