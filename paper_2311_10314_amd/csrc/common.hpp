@@ -37,10 +37,19 @@ __device__ inline T ldp(const T* plane, unsigned i) {
 // cost 15-35 %.
 template <bool NT, class T>
 __device__ inline T ldo(const T* plane, unsigned i) {
-  if constexpr (NT && sizeof(T) >= 4)
+  if constexpr (NT && sizeof(T) == 2) {
+    const unsigned short u = __builtin_nontemporal_load(
+        reinterpret_cast<const unsigned short*>(
+            reinterpret_cast<const char*>(plane) + i * 2u));
+    T v;
+    __builtin_memcpy(&v, &u, 2);
+    return v;
+  } else if constexpr (NT) {
     return __builtin_nontemporal_load(reinterpret_cast<const T*>(
         reinterpret_cast<const char*>(plane) + i * unsigned(sizeof(T))));
-  return ldp(plane, i);
+  } else {
+    return ldp(plane, i);
+  }
 }
 
 // Plane of the moving population p >= 1 of phase set i: the phase sets keep

@@ -218,7 +218,8 @@ __global__ __launch_bounds__(TX* TY) void k_frac3d(Coef<double> k,
       R mv = R(0);
       static_for<1, QF>([&](auto pc) {
         constexpr int p = decltype(pc)::value;
-        mv += R(ldp(phase_plane(b.fA, i, p, QF, k.n),
+        mv += R(ldo<MODE == MODE_STREAM && LF::c[p].x == 0>(
+            phase_plane(b.fA, i, p, QF, k.n),
                     nb.src(LF::c[p].x, LF::c[p].y, LF::c[p].z)));
       });
       psiC[i] = ldo<MODE == MODE_STREAM>(b.f0A + (long long)i * k.n, idx) + D(mv);
@@ -489,7 +490,8 @@ __device__ inline void step3d_node(const Coef<double>& kd, const Coef<R>& k,
     D sg = D(0), jd[3] = {D(0), D(0), D(0)};
     static_for<0, QG>([&](auto pc) {
       constexpr int p = decltype(pc)::value;
-      gp[p] = R(ldp(b.gA + (long long)p * n, nb.src(LG::c[p].x, LG::c[p].y, LG::c[p].z)));
+      gp[p] = R(ldo<NT && LG::c[p].x == 0>(
+          b.gA + (long long)p * n, nb.src(LG::c[p].x, LG::c[p].y, LG::c[p].z)));
       if constexpr (p > 0) sg += D(gp[p]);
       if constexpr (LG::c[p].x != 0) jd[0] += D(LG::c[p].x) * D(gp[p]);
       if constexpr (LG::c[p].y != 0) jd[1] += D(LG::c[p].y) * D(gp[p]);
@@ -634,7 +636,7 @@ __device__ inline void step3d_node(const Coef<double>& kd, const Coef<R>& k,
       R mv = R(0);
       static_for<1, QF>([&](auto pc) {
         constexpr int p = decltype(pc)::value;
-        fp[p] = R(ldp(phase_plane(b.fA, i, p, QF, n),
+        fp[p] = R(ldo<NT && LF::c[p].x == 0>(phase_plane(b.fA, i, p, QF, n),
                       nb.src(LF::c[p].x, LF::c[p].y, LF::c[p].z)));
         mv += fp[p];
       });
