@@ -50,18 +50,18 @@ PREC_BYTES = {"fp64": (8, 8), "fp32": (4, 4), "fp16": (2, 4), "bf16": (2, 4)}
 # The kernels of one step, as rocprofv3 names them (the 3D step is three
 # launches: C_i from the pulled phase populations, the chemical potential,
 # the node update; the 16-bit instances appear under their mangled names).
-KERNEL_TAGS = {
-    ("3d", "fp32"): ["k_frac3d<2, ddcc::D3Q15, float, float, float, 0, 4>",
-                     "k_mu3d<2, float, float, 4>",
+KERNEL_TAGS = {   # the 256^3 steps run in the streaming mode (3), 512^2 in 0
+    ("3d", "fp32"): ["k_frac3d<2, ddcc::D3Q15, float, float, float, 3, 4>",
+                     "k_mu3d<2, float, float, 4, true>",
                      "k_step3d<2, ddcc::D3Q15, ddcc::D3Q19, float, float, "
-                     "float, 0, 4>"],
-    ("3d", "fp64"): ["k_frac3d<2, ddcc::D3Q15, double, double, double, 0, 4>",
-                     "k_mu3d<2, double, double, 4>",
+                     "float, 3, 4>"],
+    ("3d", "fp64"): ["k_frac3d<2, ddcc::D3Q15, double, double, double, 3, 4>",
+                     "k_mu3d<2, double, double, 4, true>",
                      "k_step3d<2, ddcc::D3Q15, ddcc::D3Q19, double, double, "
-                     "double, 0, 4>"],
-    ("3d", "fp16"): ["k_frac3dILi2ENS_5D3Q15EDF16_ffLi0ELi4E",
-                     "k_mu3dILi2EDF16_fLi4E",
-                     "k_step3dILi2ENS_5D3Q15ENS_5D3Q19EDF16_ffLi0ELi4E"],
+                     "double, 3, 4>"],
+    ("3d", "fp16"): ["k_frac3dILi2ENS_5D3Q15EDF16_ffLi3ELi4E",
+                     "k_mu3dILi2EDF16_fLi4ELb1E",
+                     "k_step3dILi2ENS_5D3Q15ENS_5D3Q19EDF16_ffLi3ELi4E"],
     ("2d", "fp32"): ["k_step2d<3, float, float, float, 0, 8>"],
     ("2d", "fp64"): ["k_step2d<3, double, double, double, 0, 4>"],
 }

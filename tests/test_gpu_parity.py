@@ -213,3 +213,18 @@ def test_two_wall_channel(precision, tol):
     assert e["C"] < tol and e["u"] < tol and eP < tol
     drift = np.abs(g["mass"] - g["mass0"]) / np.abs(g["mass0"])
     assert drift.max() < (1e-12 if precision == "fp64" else 1e-6)
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 2e-6)])
+def test_porous_1024_streaming_steps(precision, tol):
+    """A 1024 x 1024 porous box moves more per step than the memory-side
+    cache holds, so the library runs its streaming step mode (nontemporal
+    stores and own-node loads): 3 steps against the oracle."""
+    wl = W.porous_bands_2d(n=1024)
+    o = oracle_run(wl, 3)
+    g = gpu_run(wl, 3, precision)
+    e = _report("porous1024 %s 3 steps" % precision, g, o)
+    fl = wl.psi >= 1e-2
+    eP = rel_linf(g["P"][fl], o["P"][fl])
+    print("P(psi>=1e-2) %.2e" % eP, flush=True)
+    assert e["C"] < tol and e["u"] < tol and eP < 100 * tol
