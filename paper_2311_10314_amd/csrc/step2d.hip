@@ -233,6 +233,7 @@ struct Step2D {
     const Patch<D> ps = patch(sm.psi, lx, ly);
     const D psi = ps.v[1][1];
     const D psih = psi > k.psi_min ? psi : k.psi_min;
+    const D ipsih = D(1) / psih;  // one division for the N phases
     D C[N], L[N];
 #pragma unroll
     for (int j = 0; j < N; ++j) {
@@ -272,7 +273,7 @@ struct Step2D {
       }
       const D pm = psi * bulk + grad + wet;
       psimu_out[i] = pm;
-      sm.mu[i][my][mx] = pm / psih;
+      sm.mu[i][my][mx] = pm * ipsih;
     }
     if constexpr (MODE != MODE_INIT) sm.T[my][mx] = R(ldp(b.TA, idx));
   }
