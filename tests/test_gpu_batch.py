@@ -128,6 +128,33 @@ def test_batched_workload_fp32_mass_and_single():
     b.close()
 
 
+def test_full_batched_workload_every_instance():
+    """The whole 256-instance workload in FP32 as the bench runs it
+    (autotuned tile, HIP-graph step loop; at 5.5 M nodes the batch runs the
+    streaming step mode): after 20 steps every instance equals a single
+    context of its own (plain mode, at most 65 536 nodes) to 1e-6 (measured:
+    bit for bit), and its phase masses are conserved to 1e-6."""
+    from paper_2311_10314_amd.ddcc import Batch
+    wls = W.batched_instances(256)
+    b = Batch.from_workloads(wls, "fp32")
+    b.autotune(3)
+    b.set_graph(10)
+    m0 = [b.mass(i) for i in range(len(wls))]
+    b.step(20)
+    worst, wi, wdrift = 0.0, -1, 0.0
+    for i, wl in enumerate(wls):
+        e = _errs(b.read_moments(i), _single(wl, 20, "fp32"))
+        d = float((np.abs(b.mass(i) - m0[i]) / np.abs(m0[i])).max())
+        wdrift = max(wdrift, d)
+        if e > worst:
+            worst, wi = e, i
+    b.close()
+    print("256 instances: worst difference to single contexts %.1e "
+          "(instance %d), worst mass drift %.1e" % (worst, wi, wdrift),
+          flush=True)
+    assert worst <= 1e-6 and wdrift < 1e-6
+
+
 def _samples():
     """Parameter samples: the same N = 2 method with different densities,
     viscosities, surface tension, mobility and body force per instance."""
