@@ -30,11 +30,12 @@ __device__ inline T ldp(const T* plane, unsigned i) {
                                      i * unsigned(sizeof(T)));
 }
 
-// Load of a value that no other node reads (the node's own history and rest
-// populations): with NT a nontemporal load, which leaves the caches to the
-// rows that neighbouring nodes share (in streaming steps: 256^3 3D about
-// 1 %, 2048^2 2D 1-2 % faster). Nontemporal loads of the shared rows too
-// cost 15-35 %.
+// Load of a value that only this node reads in the step (its own history
+// and rest populations; in 3D also a pulled population whose row is not
+// shifted in x, so that no neighbouring tile touches its cache lines): with
+// NT a nontemporal load, which leaves the caches to the rows that
+// neighbouring nodes share (in streaming steps: 256^3 3D 1-2 %, 2048^2 2D
+// 1-2 % faster). Nontemporal loads of the shared rows too cost 15-35 %.
 template <bool NT, class T>
 __device__ inline T ldo(const T* plane, unsigned i) {
   if constexpr (NT && sizeof(T) == 2) {
