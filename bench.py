@@ -88,12 +88,23 @@ def algorithmic_bytes_per_node(N, dim, Qf, Qg, precision, rest64=False):
     return pops + (hist + tens + static) * fesz
 
 
+def _code_only(text):
+    """C++ source without its comments and blank space, so that a change
+    of comments alone does not mark the counters as stale."""
+    import re
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
 def kernel_source_hash(kind):
+    """Hash of the code (comments and spacing removed) of the sources the
+    step kernels of `kind` are built from."""
     import hashlib
     h = hashlib.sha256()
     for rel in KERNEL_SOURCES[kind]:
-        with open(os.path.join(ROOT, rel), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, rel), encoding="utf-8") as fh:
+            h.update(_code_only(fh.read()).encode())
     return h.hexdigest()[:16]
 
 
