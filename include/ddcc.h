@@ -153,7 +153,9 @@ int ddcc_init_fields_dev(ddcc_ctx* ctx, const double* C_dev,
 /* Advances nsteps >= 0 time steps (eqs. 3.1, 3.2), asynchronously on the
  * context stream: in 2D one fused kernel per step; in 3D three, one forming
  * C_i from the pulled phase populations, one z-marching kernel for the
- * chemical potential mu_i, and one z-marching kernel for the node update. */
+ * chemical potential mu_i, and one z-marching kernel for the node update.
+ * Contexts whose step moves more than the 256 MB memory-side cache run the
+ * same kernels with nontemporal stores (same results). */
 int ddcc_step(ddcc_ctx* ctx, int64_t nsteps);
 
 /* C_i, u and P of the current time level (moment recovery of Section 3 and
