@@ -235,16 +235,24 @@ def test_d3q7_short_run(precision, tol):
     assert drift.max() < (1e-12 if precision == "fp64" else 1e-6)
 
 
-def test_n3_streaming_steps():
-    """A 64 x 72 x 96 box with three phases moves more per step than the
-    memory-side cache holds (about 290 MiB in FP32, 560 MiB in FP64), so the
-    library runs its streaming step mode: 2 steps against one oracle run,
-    FP64 within 1e-12, FP32 within 2e-6 (C, u, and P where psi >= 1e-2)."""
-    wl = W.random_small(3, 3, (64, 72, 96), seed=41)
-    print("random 3D 64x72x96 N=3, 2 steps", flush=True)
+@pytest.mark.parametrize("N,shape,precisions", [
+    (3, (64, 72, 96), ("fp64", "fp32")),
+    (2, (61, 66, 70), ("fp64",))])
+def test_streaming_steps(N, shape, precisions):
+    """Boxes that move more per step than the memory-side cache holds run
+    the streaming step mode: 64 x 72 x 96 with three phases (about 290 MiB
+    per step in FP32, 560 MiB in FP64), and 61 x 66 x 70 with two (FP64,
+    about 280 MiB; nz = 61, ny = 66 and nx = 70 leave the last z column, tile
+    row and tile partly filled). 2 steps
+    against one oracle run, FP64 within 1e-12, FP32 within 2e-6 (C, u, and P
+    where psi >= 1e-2)."""
+    wl = W.random_small(3, N, shape, seed=41)
+    print("random 3D %s N=%d, 2 steps" % ("x".join(map(str, shape)), N),
+          flush=True)
     o = oracle_run(wl, 2)
     fl = np.asarray(wl.psi) >= 1e-2
-    for precision, tol in (("fp64", 1e-12), ("fp32", 2e-6)):
+    for precision in precisions:
+        tol = 1e-12 if precision == "fp64" else 2e-6
         g = gpu_run(wl, 2, precision)
         g["sim"].close()
         e = _err(g, o)
