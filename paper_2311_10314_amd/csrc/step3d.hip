@@ -441,12 +441,58 @@ __device__ inline Star<double> lds_star(const Pl* const* pz, int lx, int ly,
   return s;
 }
 
+// What the node update reads at its own node, in their storage types: the
+// pulled populations of every set, the float64 rest populations and the
+// history. With FP32 storage the kernel loads them one plane ahead (below).
+template <int N, class LF, class LG, class Pop, class S>
+struct NodeIn {
+  Pop g[LG::Q];
+  Pop f[N][LF::Q - 1];
+  double f0[N];
+  S hC[N], hU[3], hM[3], hP;
+};
+
+template <int N, class LF, class LG, class Pop, class S, int MODE>
+__device__ inline void fetch_node(const Bufs<Pop, S>& b, long long n, int nx,
+                                  int ny, int nz, int x, int y, int z,
+                                  NodeIn<N, LF, LG, Pop, S>& in) {
+  if constexpr (MODE != MODE_INIT) {
+    constexpr bool NT = MODE == MODE_STREAM;
+    constexpr int QF = LF::Q;
+    const Nbr3 nb = make_nbr3(x, y, z, nx, ny, nz);
+    const unsigned idx = nb.at(0, 0, 0);
+    static_for<0, LG::Q>([&](auto pc) {
+      constexpr int p = decltype(pc)::value;
+      in.g[p] = ldo<NT && LG::c[p].x == 0>(
+          b.gA + (long long)p * n, nb.src(LG::c[p].x, LG::c[p].y, LG::c[p].z));
+    });
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      static_for<1, QF>([&](auto pc) {
+        constexpr int p = decltype(pc)::value;
+        in.f[i][p - 1] = ldo<NT && LF::c[p].x == 0>(
+            phase_plane(b.fA, i, p, QF, n),
+            nb.src(LF::c[p].x, LF::c[p].y, LF::c[p].z));
+      });
+      in.f0[i] = ldo<NT>(b.f0A + (long long)i * n, idx);
+      in.hC[i] = ldo<NT>(b.hist + (long long)(H3_C + i) * n, idx);
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      in.hU[a] = ldo<NT>(b.hist + (long long)(H3_U<N> + a) * n, idx);
+      in.hM[a] = ldo<NT>(b.hist + (long long)(H3_M<N> + a) * n, idx);
+    }
+    in.hP = ldo<NT>(b.hist + (long long)(H3_P<N>) * n, idx);
+  }
+}
+
 template <int N, class LF, class LG, class Pop, class S, class R, int MODE,
-          int TY>
+          int TY, bool PRE, class PF>
 __device__ inline void step3d_node(const Coef<double>& kd, const Coef<R>& k,
                                    const Bufs<Pop, S>& b, int x, int y, int z,
                                    const StepPlane<N, TY>* const* pz, int lx,
-                                   int ly) {
+                                   int ly, const NodeIn<N, LF, LG, Pop, S>& in,
+                                   PF prefetch) {
   using D = double;
   using Pl = StepPlane<N, TY>;
   constexpr int QF = LF::Q, QG = LG::Q;
@@ -545,8 +591,11 @@ __device__ inline void step3d_node(const Coef<double>& kd, const Coef<R>& k,
     D sg = D(0), jd[3] = {D(0), D(0), D(0)};
     static_for<0, QG>([&](auto pc) {
       constexpr int p = decltype(pc)::value;
-      gp[p] = R(ldo<NT && LG::c[p].x == 0>(
-          b.gA + (long long)p * n, nb.src(LG::c[p].x, LG::c[p].y, LG::c[p].z)));
+      if constexpr (PRE)
+        gp[p] = R(in.g[p]);
+      else
+        gp[p] = R(ldo<NT && LG::c[p].x == 0>(
+            b.gA + (long long)p * n, nb.src(LG::c[p].x, LG::c[p].y, LG::c[p].z)));
       if constexpr (p > 0) sg += D(gp[p]);
       if constexpr (LG::c[p].x != 0) jd[0] += D(LG::c[p].x) * D(gp[p]);
       if constexpr (LG::c[p].y != 0) jd[1] += D(LG::c[p].y) * D(gp[p]);
@@ -556,7 +605,8 @@ __device__ inline void step3d_node(const Coef<double>& kd, const Coef<R>& k,
     const R j[3] = {R(jd[0]), R(jd[1]), R(jd[2])};
     // force (eq. 3.13): -div T^{n-1} + sum_i phi mu_i grad C_i
     //                   + P^{n-1} grad psi + psi (rho a + G)
-    const R Pprev = R(ldo<NT>(b.hist + (long long)(H3_P<N>) * n, idx));
+    const R Pprev =
+        R(PRE ? in.hP : ldo<NT>(b.hist + (long long)(H3_P<N>) * n, idx));
     R Fp[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -585,8 +635,8 @@ __device__ inline void step3d_node(const Coef<double>& kd, const Coef<R>& k,
     R uprev[3], mprev[3], Yprev[6];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      uprev[a] = R(ldp(b.hist + (long long)(H3_U<N> + a) * n, idx));
-      mprev[a] = R(ldo<NT>(b.hist + (long long)(H3_M<N> + a) * n, idx));
+      uprev[a] = R(PRE ? in.hU[a] : ldp(b.hist + (long long)(H3_U<N> + a) * n, idx));
+      mprev[a] = R(PRE ? in.hM[a] : ldo<NT>(b.hist + (long long)(H3_M<N> + a) * n, idx));
     }
     sym_flux(psi, mprev, uprev, Yprev);
 #pragma unroll
@@ -622,6 +672,7 @@ __device__ inline void step3d_node(const Coef<double>& kd, const Coef<R>& k,
 #pragma unroll
     for (int a = 0; a < 3; ++a) stp<NT>(b.outU + a * n, idx, double(u[a]));
     stp<NT>(b.outP, idx, double(P));
+    prefetch();
     return;
   }
 
@@ -691,19 +742,24 @@ __device__ inline void step3d_node(const Coef<double>& kd, const Coef<R>& k,
       R mv = R(0);
       static_for<1, QF>([&](auto pc) {
         constexpr int p = decltype(pc)::value;
-        fp[p] = R(ldo<NT && LF::c[p].x == 0>(phase_plane(b.fA, i, p, QF, n),
-                      nb.src(LF::c[p].x, LF::c[p].y, LF::c[p].z)));
+        if constexpr (PRE)
+          fp[p] = R(in.f[i][p - 1]);
+        else
+          fp[p] = R(ldo<NT && LF::c[p].x == 0>(phase_plane(b.fA, i, p, QF, n),
+                        nb.src(LF::c[p].x, LF::c[p].y, LF::c[p].z)));
         mv += fp[p];
       });
-      const D f0 = ldo<NT>(b.f0A + (long long)i * n, idx);
+      const D f0 = PRE ? in.f0[i] : ldo<NT>(b.f0A + (long long)i * n, idx);
       const R psiC = R(f0 + D(mv));
       // phi C_i u of the previous step from its stored factors (phi C_i is
       // read before this step overwrites it)
-      const R psiCprev = R(ldo<NT>(b.hist + (long long)(H3_C + i) * n, idx));
+      const R psiCprev =
+          R(PRE ? in.hC[i] : ldo<NT>(b.hist + (long long)(H3_C + i) * n, idx));
       R Xprev[3];
 #pragma unroll
       for (int a = 0; a < 3; ++a)
-        Xprev[a] = psiCprev * R(ldp(b.hist + (long long)(H3_U<N> + a) * n, idx));
+        Xprev[a] = psiCprev * R(PRE ? in.hU[a]
+                                    : ldp(b.hist + (long long)(H3_U<N> + a) * n, idx));
       const R X[3] = {psiC * u[0], psiC * u[1], psiC * u[2]};
       // S_i (eq. 3.7) and V = d_t(phi C_i u) + c_s^2 eta (mu grad psi - S_i)
       R V[3];
@@ -735,6 +791,9 @@ __device__ inline void step3d_node(const Coef<double>& kd, const Coef<R>& k,
   stp<NT>(b.hist + (long long)(H3_P<N>) * n, idx, S(P));
 #pragma unroll
   for (int c = 0; c < 3; ++c) stp<NT>(b.TB + (long long)c * n, idx, S(Tn[c]));
+  // every input of this node has been used: the next plane's node loads go
+  // into the same registers
+  prefetch();
 }
 
 // Waves per SIMD the register allocation aims at: what the LDS ring allows
@@ -805,21 +864,100 @@ void k_step3d(Coef<double> kda, Coef<R> ka,
     }
   };
 
+  // FP32 storage: a software pipeline over the planes of the column. The
+  // node's own inputs (NodeIn) for plane z + 1 are loaded at the end of the
+  // node update of plane z, into the registers that plane z's inputs have
+  // just freed, and plane z + 2 of the ring is fetched into registers before
+  // plane z is computed and put into LDS after it. The node update then
+  // waits only for the lagged-T gathers; before, each plane waited for its
+  // ring load (behind the previous plane's stores), its gathers and flow
+  // populations, then its phase populations. 169 -> 253 VGPRs, still two
+  // waves per SIMD; 256^3 FP32 2.476 -> 2.352 ms per step (same box, bit for
+  // bit the same results). Measured and left out: the node loads alone
+  // (2.418 ms), also the T gathers one plane ahead (10 VGPRs spilled, 2.436
+  // ms), and the pipeline for the 16-bit storages, whose node update at 161
+  // to 165 VGPRs runs three waves per SIMD and drops to two with it (FP16
+  // 1.655 -> 1.772 ms, BF16 1.696 -> 1.807 ms). FP64 (253 VGPRs without it)
+  // has no room.
+  using In = NodeIn<N, LF, LG, Pop, S>;
+  constexpr bool PF = std::is_same_v<Pop, float> && MODE != MODE_INIT;
+  constexpr bool RF = PF;
+  In cur;
+  if constexpr (PF)
+    if (own) fetch_node<N, LF, LG, Pop, S, MODE>(b, k.n, nx, ny, nz, x, y, z0, cur);
+  constexpr int PER = (HN + TX * TY - 1) / (TX * TY);  // ring slots per thread
+  S pre[PER][2 * N + 1];
+  auto fetch_ring = [&](int zz) {
+    const int zw = wrap(zz, nz);
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int r = int(threadIdx.x) + u * TX * TY;
+      if (r < HN) {
+        const int ly = r / HX, lx = r - ly * HX;
+        const unsigned i0 = (unsigned(zw) * unsigned(ny) +
+                             unsigned(wrap(y0 + ly - 1, ny))) * unsigned(nx) +
+                            unsigned(wrap(x0 + lx - 1, nx));
+        pre[u][2 * N] = ldp(b.psi, i0);
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+          pre[u][j] = ldp(work_field<S>(b.fC) + (long long)j * k.n, i0);
+          pre[u][N + j] = ldp(work_field<S>(b.fmu) + (long long)j * k.n, i0);
+        }
+      }
+    }
+  };
+  auto put_ring = [&](Pl& pl) {
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int r = int(threadIdx.x) + u * TX * TY;
+      if (r < HN) {
+        const int ly = r / HX, lx = r - ly * HX;
+        pl.p[ly][lx] = double(pre[u][2 * N]);
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+          pl.c[j][ly][lx] = double(pre[u][j]);
+          pl.m[j][ly][lx] = double(pre[u][N + j]);
+        }
+      }
+    }
+  };
+
   load(z0 - 1, ring[(z0 + 2) % 3]);
   load(z0, ring[z0 % 3]);
-  for (int z = z0; z < z1; ++z) {
-    load(z + 1, ring[(z + 1) % 3]);
+  if constexpr (RF) {
+    load(z0 + 1, ring[(z0 + 1) % 3]);
     __syncthreads();
+  }
+  for (int z = z0; z < z1; ++z) {
+    const bool more = z + 1 < z1;
+    if constexpr (RF) {
+      if (more) fetch_ring(z + 2);
+    } else {
+      load(z + 1, ring[(z + 1) % 3]);
+      __syncthreads();
+    }
     if (own) {
       const Pl* pz[3] = {&ring[(z + 2) % 3], &ring[z % 3], &ring[(z + 1) % 3]};
-      step3d_node<N, LF, LG, Pop, S, R, MODE, TY>(kd, k, b, x, y, z, pz,
-                                                 tx + 1, ty + 1);
+      if constexpr (PF) {
+        step3d_node<N, LF, LG, Pop, S, R, MODE, TY, true>(
+            kd, k, b, x, y, z, pz, tx + 1, ty + 1, cur, [&] {
+              if (more)
+                fetch_node<N, LF, LG, Pop, S, MODE>(b, k.n, nx, ny, nz, x, y,
+                                                    z + 1, cur);
+            });
+      } else {
+        step3d_node<N, LF, LG, Pop, S, R, MODE, TY, false>(
+            kd, k, b, x, y, z, pz, tx + 1, ty + 1, cur, [] {});
+      }
     }
-    // the slot of plane z - 1 is overwritten by the next iteration's load.
-    // (Fetching plane z + 2 into registers during the node update, as
-    // k_mu3d does, takes the float kernels past their register budget:
-    // 256^3 FP32 2.53 -> 3.14 ms, FP16 1.71 -> 1.89 ms, same box.)
+    // the slot of plane z - 1 is overwritten next
     __syncthreads();
+    if constexpr (RF) {
+      if (more) {
+        put_ring(ring[(z + 2) % 3]);
+        __syncthreads();
+      }
+    }
   }
 }
 
