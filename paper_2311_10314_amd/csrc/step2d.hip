@@ -221,12 +221,26 @@ struct Step2D {
     sm.prho[ly][lx] = psi * rho;
   }
 
-  // Phase 2 at mu-region coordinates (mx, my): phi mu_i (eq. 2.14).
+  // Phase-2 inputs from global memory, issued in phase 1: the lagged T
+  // into LDS and the wetting weights E_i into registers.
   template <class G>
+  __device__ static inline void load2(Smem& sm, const Bufs<Pop, S>& b,
+                                      const G& gd, int x0, int y0, int mx,
+                                      int my, S* E) {
+    const int gx = wrap(x0 + mx - 1, gd.nx), gy = wrap(y0 + my - 1, gd.ny);
+    const unsigned idx = gd.off + unsigned(gy * gd.nx + gx);
+#pragma unroll
+    for (int i = 0; i < N - 1; ++i) E[i] = ldp(b.wet + (long long)(i) * gd.n, idx);
+    if constexpr (MODE != MODE_INIT) sm.T[my][mx] = R(ldp(b.TA, idx));
+  }
+
+  // Phase 2 at mu-region coordinates (mx, my): phi mu_i (eq. 2.14).
+  template <bool PRE2 = false, class G>
   __device__ static inline void node2(Smem& sm, const Coef<D>& k,
                                       const Bufs<Pop, S>& b, const G& gd, int x0,
                                       int y0, int mx,
-                                      int my, D* psimu_out) {
+                                      int my, D* psimu_out,
+                                      const S* E = nullptr) {
     const int lx = mx + 1, ly = my + 1;
     const int gx = wrap(x0 + mx - 1, gd.nx), gy = wrap(y0 + my - 1, gd.ny);
     const unsigned idx = gd.off + unsigned(gy * gd.nx + gx);
@@ -245,7 +259,8 @@ struct Step2D {
     // E_i = sum_k cos theta^k_iN |grad psi_k| (eq. 2.9 is linear in them)
     D ct[N];
 #pragma unroll
-    for (int i = 0; i < N - 1; ++i) ct[i] = D(ldp(b.wet + (long long)(i) * gd.n, idx));
+    for (int i = 0; i < N - 1; ++i)
+      ct[i] = PRE2 ? D(E[i]) : D(ldp(b.wet + (long long)(i) * gd.n, idx));
     ct[N - 1] = D(0);
     D W[N];  // sum_{q != j} (sum_k cos theta^k_jq |grad psi_k|) C_j C_q
 #pragma unroll
@@ -275,7 +290,7 @@ struct Step2D {
       psimu_out[i] = pm;
       sm.mu[i][my][mx] = pm * ipsih;
     }
-    if constexpr (MODE != MODE_INIT) sm.T[my][mx] = R(ldp(b.TA, idx));
+    if constexpr (MODE != MODE_INIT && !PRE2) sm.T[my][mx] = R(ldp(b.TA, idx));
   }
 
   __device__ static void run(const Coef<D>& kd, const Coef<R>& k,
@@ -302,6 +317,10 @@ struct Step2D {
                                         : r * (q + 1u) + (xc - r) * q + j);
       x0 = int(t % gx) * TX;
       y0 = int(t / gx) * TY;
+    }
+    if constexpr (MODE == MODE_STREAM) {
+      body(sm, kd, k, b, Grid{k.nx, k.ny, k.n, 0u}, x0, y0);
+      return;
     }
     const int tid = threadIdx.x;
     const int tx = tid % TX, ty = tid / TX;
@@ -332,6 +351,66 @@ struct Step2D {
                   psiC, psimu_d, &fown);
   }
 
+  // The tile of a streaming step (grids larger than the memory-side cache).
+  // Vector-memory completion is counted in issue order, so each phase above
+  // waits for its own loads: the pulls in phase 1, T and the wetting weights
+  // in phase 2, the flow populations and history in phase 3. Here phase 2's
+  // loads go out in phase 1 (T straight into LDS, E_i into registers) and
+  // the own node's phase-3 loads before the second barrier, so a tile waits
+  // on memory once in phase 1 and once, overlapped by the barrier and the
+  // LDS gradients, in phase 3. Same box, same results bit for bit, ms per
+  // step: porous 2048^2 N = 3 FP32 0.389 -> 0.377, FP64 0.758 -> 0.709;
+  // disk 2048^2 N = 2 FP32 0.283 -> 0.265, FP64 0.499 -> 0.496; disk 4096^2
+  // FP32 1.136 -> 1.080, FP64 2.130 -> 2.158; 256 batched instances 0.400
+  // -> 0.381. On the cache-resident 512^2 box the plain order stays (porous
+  // FP32 22.7 -> 24.0 us, FP64 41.3 -> 42.1 us with this one). Phase 2's
+  // loads moved alone: porous 2048^2 FP32 0.394, FP64 0.746, batch 0.395.
+  __device__ static inline void body(Smem& sm, const Coef<D>& kd,
+                                     const Coef<R>& k, const Bufs<Pop, S>& b,
+                                     const Grid& gd, int x0, int y0) {
+    const int tid = threadIdx.x;
+    const int tx = tid % TX, ty = tid / TX;
+    constexpr bool KEEP = MODE == MODE_STEP || MODE == MODE_STREAM;
+    constexpr int PER2 = (RING2 + NT - 1) / NT;
+    D psiC[N], psimu_d[N], dummy[N];
+    S Eown[N], Er[PER2][N];
+    Keep fown;
+    node1<KEEP>(sm, kd, b, gd, x0, y0, tx + 2, ty + 2, psiC, &fown);
+    load2(sm, b, gd, x0, y0, tx + 1, ty + 1, Eown);
+#pragma unroll
+    for (int u = 0; u < PER2; ++u) {
+      const int r = tid + u * NT;
+      if (r < RING2) {
+        int mx, my;
+        ring2(r, mx, my);
+        load2(sm, b, gd, x0, y0, mx, my, Er[u]);
+      }
+    }
+    for (int r = tid; r < RING1; r += NT) {
+      int lx, ly;
+      ring1(r, lx, ly);
+      node1(sm, kd, b, gd, x0, y0, lx, ly, dummy);
+    }
+    __syncthreads();
+    node2<true>(sm, kd, b, gd, x0, y0, tx + 1, ty + 1, psimu_d, Eown);
+#pragma unroll
+    for (int u = 0; u < PER2; ++u) {
+      const int r = tid + u * NT;
+      if (r < RING2) {
+        int mx, my;
+        ring2(r, mx, my);
+        node2<true>(sm, kd, b, gd, x0, y0, mx, my, dummy, Er[u]);
+      }
+    }
+    const bool own = x0 + tx < gd.nx && y0 + ty < gd.ny;
+    In3 in3;
+    if (own) load3(b, gd, x0, y0, tx, ty, in3);
+    __syncthreads();
+    if (own)
+      node3<KEEP, true>(sm, kd, k, b, gd, x0, y0, tx, ty, psiC, psimu_d,
+                        &fown, &in3);
+  }
+
   // One TX x TY tile with its corner at (x0, y0) of box gd. Every thread of
   // the workgroup passes both barriers; there is no early return, so a
   // workgroup can process several tiles in a row.
@@ -339,6 +418,10 @@ struct Step2D {
                               const Bufs<Pop, S>& b, const Grid& gd, int x0,
                               int y0) {
     __shared__ Smem sm;
+    if constexpr (MODE == MODE_STREAM) {
+      body(sm, kd, k, b, gd, x0, y0);
+      return;
+    }
     const int tid = threadIdx.x;
     const int tx = tid % TX, ty = tid / TX;
     D psiC[N], psimu_d[N], dummy[N];
@@ -364,13 +447,41 @@ struct Step2D {
       node3<KEEP>(sm, kd, k, b, gd, x0, y0, tx, ty, psiC, psimu_d, &fown);
   }
 
+  // Phase-3 inputs of the own node from global memory (flow populations,
+  // history, float64 rest populations), issued before the second barrier.
+  struct In3 {
+    Pop g[Q];
+    S hX[2 * N], hY[3], hP;
+    D f0[N];
+  };
+  __device__ static inline void load3(const Bufs<Pop, S>& b, const Grid& gd,
+                                      int x0, int y0, int tx, int ty, In3& in) {
+    if constexpr (MODE != MODE_INIT) {
+      const int gx = x0 + tx, gy = y0 + ty;
+      const long long n = gd.n;
+      const unsigned idx = gd.off + unsigned(gy * gd.nx + gx);
+      const Nbr nb = make_nbr(gx, gy, gd.nx, gd.ny, gd.off);
+#pragma unroll
+      for (int p = 0; p < Q; ++p)
+        in.g[p] = ldp(b.gA + (long long)p * n, nb.src(D2Q9::c[p].x, D2Q9::c[p].y));
+#pragma unroll
+      for (int q = 0; q < 2 * N; ++q) in.hX[q] = ldo<STREAM>(b.hist + (long long)q * n, idx);
+#pragma unroll
+      for (int q = 0; q < 3; ++q) in.hY[q] = ldo<STREAM>(b.hist + (long long)(2 * N + q) * n, idx);
+      in.hP = ldo<STREAM>(b.hist + (long long)(2 * N + 3) * n, idx);
+#pragma unroll
+      for (int i = 0; i < N; ++i) in.f0[i] = ldp(b.f0A + (long long)(i) * n, idx);
+    }
+  }
+
   // Phase 3 for the own node (x0 + tx, y0 + ty) of the tile.
-  template <bool KEPT = false>
+  template <bool KEPT = false, bool PRE3 = false>
   __device__ static inline void node3(const Smem& sm, const Coef<D>& kd,
                                       const Coef<R>& k, const Bufs<Pop, S>& b,
                                       const Grid& gd, int x0, int y0, int tx,
                                       int ty, const D* psiC, const D* psimu_d,
-                                      const Keep* kept = nullptr) {
+                                      const Keep* kept = nullptr,
+                                      const In3* in3 = nullptr) {
     R psimu[N];
 #pragma unroll
     for (int i = 0; i < N; ++i) psimu[i] = R(psimu_d[i]);
@@ -436,7 +547,10 @@ struct Step2D {
       R j[2] = {R(0), R(0)};
 #pragma unroll
       for (int p = 0; p < Q; ++p) {
-        gp[p] = R(ldp(b.gA + (long long)p * n, nb.src(D2Q9::c[p].x, D2Q9::c[p].y)));
+        if constexpr (PRE3)
+          gp[p] = R(in3->g[p]);
+        else
+          gp[p] = R(ldp(b.gA + (long long)p * n, nb.src(D2Q9::c[p].x, D2Q9::c[p].y)));
         if (p > 0) sum_gm += gp[p];
         if (D2Q9::c[p].x) j[0] += R(D2Q9::c[p].x) * gp[p];
         if (D2Q9::c[p].y) j[1] += R(D2Q9::c[p].y) * gp[p];
@@ -444,7 +558,7 @@ struct Step2D {
       // force (eq. 3.13): -div T^{n-1} + sum_i phi mu_i grad C_i
       //                   + P^{n-1} grad psi + psi (rho a + G)
       const Patch<R> tp = patch(sm.T, mx, my);
-      const R Pprev = R(ldo<STREAM>(b.hist + (long long)(2 * N + 3) * n, idx));
+      const R Pprev = R(PRE3 ? in3->hP : ldo<STREAM>(b.hist + (long long)(2 * N + 3) * n, idx));
       R Fp[2];
       Fp[0] = grad_y(tp) + Pprev * gpsi[0] + psirho * k.accel[0] +
               psi * k.force[0];
@@ -473,7 +587,7 @@ struct Step2D {
     if constexpr (MODE != MODE_INIT) {
 #pragma unroll
       for (int q = 0; q < 3; ++q)
-        dtY[q] = Y[q] - R(ldo<STREAM>(b.hist + (long long)(2 * N + q) * n, idx));
+        dtY[q] = Y[q] - R(PRE3 ? in3->hY[q] : ldo<STREAM>(b.hist + (long long)(2 * N + q) * n, idx));
     }
 
     // local flow rates from nu (eq. 16)
@@ -567,8 +681,8 @@ struct Step2D {
           }
         Sx *= psi;
         Sy *= psi;
-        const R dX0 = X[0] - R(ldo<STREAM>(b.hist + (long long)(2 * i) * n, idx));
-        const R dX1 = X[1] - R(ldo<STREAM>(b.hist + (long long)(2 * i + 1) * n, idx));
+        const R dX0 = X[0] - R(PRE3 ? in3->hX[2 * i] : ldo<STREAM>(b.hist + (long long)(2 * i) * n, idx));
+        const R dX1 = X[1] - R(PRE3 ? in3->hX[2 * i + 1] : ldo<STREAM>(b.hist + (long long)(2 * i + 1) * n, idx));
         const R V[2] = {dX0 + k.cs2 * k.eta[i] * (mu[i] * gpsi[0] - Sx),
                         dX1 + k.cs2 * k.eta[i] * (mu[i] * gpsi[1] - Sy)};
         R fp[Q];
@@ -588,7 +702,7 @@ struct Step2D {
           stp<STREAM>(phase_plane(b.fB, i, p, Q, n), idx,
               narrow<Pop>(fp[p] - del[p], comp));
         stp<STREAM>(b.f0B + (long long)(i) * n, idx,
-            ldp(b.f0A + (long long)(i) * n, idx) - D(del[0]) + comp);
+            (PRE3 ? in3->f0[i] : ldp(b.f0A + (long long)(i) * n, idx)) - D(del[0]) + comp);
       }
       stp<STREAM>(b.hist + (long long)(2 * i) * n, idx, S(X[0]));
       stp<STREAM>(b.hist + (long long)(2 * i + 1) * n, idx, S(X[1]));
