@@ -228,3 +228,24 @@ def test_porous_1024_streaming_steps(precision, tol):
     eP = rel_linf(g["P"][fl], o["P"][fl])
     print("P(psi>=1e-2) %.2e" % eP, flush=True)
     assert e["C"] < tol and e["u"] < tol and eP < 100 * tol
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 2e-6)])
+def test_ragged_streaming_steps(precision, tol):
+    """A 790 x 830 box with three phases and random smooth fields moves
+    more per step than the 256 MB memory-side cache (about 278 MB in FP32,
+    524 MB in FP64), so it runs the streaming step mode with its own tile
+    load order (phase-2 loads in phase 1, the own node's phase-3 loads
+    before the second barrier), here on partial tiles in x (830 = 12 x 64
+    + 62) and y (790 rows: 98 x 8 + 6 in FP32, 197 x 4 + 2 in FP64):
+    2 steps against the oracle."""
+    wl = W.random_small(2, 3, (790, 830), seed=29)
+    o = oracle_run(wl, 2)
+    g = gpu_run(wl, 2, precision)
+    e = _report("ragged 790x830 %s 2 steps" % precision, g, o)
+    fl = wl.psi >= 1e-2
+    eP = rel_linf(g["P"][fl], o["P"][fl])
+    print("P(psi>=1e-2) %.2e" % eP, flush=True)
+    assert e["C"] < tol and e["u"] < tol and eP < 100 * tol
+    drift = np.abs(g["mass"] - g["mass0"]) / np.abs(g["mass0"])
+    assert drift.max() < (1e-12 if precision == "fp64" else 1e-6)
