@@ -6,19 +6,22 @@ Headline workload: the 3D droplet impacting a sphere, 256^3 periodic box
 (sphere R = 60, droplet R = 40 moving at 0.02 towards it, density ratio 10,
 90 deg walls), N = 2 phase sets on D3Q15 and a D3Q19 flow set, FP32 storage
 and arithmetic: the largest single-GPU configuration of the paper's
-setting. One "step" is one time step of the whole scheme (one kernel
-launch, k_step3d). The JSON `value` is its node-MLUPS; `roofline` prices
-the kernel against the 8 TB/s HBM peak with the algorithmic bytes of one
-node update (populations read and written once, history read and written
-once, psi and the wetting weight read once: 528 B at N = 2 in FP32, 544 B
-counting the float64 rest planes the library keeps) over the average
-launch duration from HIP events on the library's stream.
+setting. One "step" is one time step of the whole scheme (three kernel
+launches: k_frac3d, k_mu3d, k_step3d). The JSON `value` is its node-MLUPS;
+`roofline` prices the step against the 8 TB/s HBM peak with the algorithmic
+bytes of one node update (populations read and written once, history read
+and written once, psi and the wetting weight read once: 528 B at N = 2 in
+FP32, 544 B counting the float64 rest planes the library keeps) over the
+average step duration from HIP events on the library's stream.
 
 Other legs in the same line: the 3D box in FP64 and with 16-bit population
 storage, the 2D porous box (512 x 512, N = 3; it fits the 256 MB
-memory-side cache, so its rate is not an HBM roofline figure), the batch of
-256 independent 2D boxes, and the adjoint sweep. Every leg carries its
-error against the FP64 oracle and its mass drift.
+memory-side cache, so its rate is not an HBM roofline figure) and the same
+porous generator at 2048 x 2048 (streamed from HBM), the batch of 256
+independent 2D boxes, and the adjoint sweep. Each leg carries its mass
+drift, and its error against the FP64 oracle from this run (the 2048^2 box
+is too large for the oracle here; its kernels are the ones the streaming
+parity tests check).
 """
 import argparse
 import json
@@ -657,6 +660,10 @@ def main():
     ap.add_argument("--precisions", default="fp32,fp64,fp16,bf16",
                     help="3D precisions to time (the first is not repeated)")
     ap.add_argument("--no-2d", action="store_true")
+    ap.add_argument("--porous-hbm", type=int, default=2048,
+                    help="side of the 2D porous box timed at an HBM size "
+                         "(0: skip)")
+    ap.add_argument("--porous-hbm-steps", type=int, default=200)
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--sweep", metavar="OUT_JSON", nargs="?", const="",
                     default=None,
@@ -744,6 +751,34 @@ def main():
             print("  porous 512^2 %s: %.4f ms/step" % (prec, ms2),
                   file=sys.stderr, flush=True)
 
+    # ---- 2D porous box at an HBM size (streaming step mode) ----------------
+    porous_hbm = None
+    if not a.no_2d and a.porous_hbm > 0:
+        n3 = a.porous_hbm
+        wl3 = W.porous_bands_2d(n=n3)
+        porous_hbm = {"workload": "porous_bands_2d %dx%d, N=3 (+1 flow set), "
+                                  "D2Q9, rho 1:10:100" % (n3, n3),
+                      "note": "streams from HBM (the library's streaming "
+                              "step mode); the same kernels as the 1024^2 "
+                              "and 790x830 streaming parity tests; no "
+                              "counter run for this box (traffic null)"}
+        for prec in ("fp32", "fp64"):
+            s3, ms3, dr3 = time_gpu(wl3, prec, a.porous_hbm_steps, 10, torch)
+            s3.close()
+            r = roofline("2d", prec, wl3.nodes, ms3, 3, 2, 9, 9, torch)
+            r["traffic"] = None
+            r["kernels"] = ["k_step2d<3, float, float, float, 3, 8>"
+                            if prec == "fp32" else
+                            "k_step2d<3, double, double, double, 3, 4>"]
+            porous_hbm[prec] = {"value": wl3.nodes / (ms3 * 1e-3) / 1e6,
+                                "unit": "MLUPS", "ms_per_step": ms3,
+                                "steps": a.porous_hbm_steps,
+                                "mass_drift": dr3, "roofline": r}
+            print("  porous %d^2 %s: %.4f ms/step, %.0f GB/s algorithmic "
+                  "(%.3f of peak)" % (n3, prec, ms3, r["achieved"], r["frac"]),
+                  file=sys.stderr, flush=True)
+        del wl3
+
     batched = None
     if a.batch:
         print("timing %d batched instances" % a.batch, file=sys.stderr,
@@ -803,6 +838,7 @@ def main():
         "error_vs_oracle": err,
         "sphere3d": legs3,
         "porous2d": porous,
+        "porous2d_hbm": porous_hbm,
         "batched": batched,
         "adjoint": adjoint,
     }
