@@ -231,18 +231,21 @@ def test_porous_1024_streaming_steps(precision, tol):
 
 
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 2e-6)])
-def test_ragged_streaming_steps(precision, tol):
-    """A 790 x 830 box with three phases and random smooth fields moves
-    more per step than the 256 MB memory-side cache (about 278 MB in FP32,
-    524 MB in FP64), so it runs the streaming step mode with its own tile
-    load order (phase-2 loads in phase 1, the own node's phase-3 loads
-    before the second barrier), here on partial tiles in x (830 = 12 x 64
-    + 62) and y (790 rows: 98 x 8 + 6 in FP32, 197 x 4 + 2 in FP64):
-    2 steps against the oracle."""
-    wl = W.random_small(2, 3, (790, 830), seed=29)
+@pytest.mark.parametrize("N,shape,seed", [(3, (790, 830), 29),
+                                          (4, (700, 740), 31)])
+def test_ragged_streaming_steps(precision, tol, N, shape, seed):
+    """Boxes with random smooth fields that move more per step than the
+    256 MB memory-side cache (N = 3, 790 x 830: about 278 MB in FP32 and
+    524 MB in FP64; N = 4, 700 x 740: 273 and 514 MB), so they run the
+    streaming step mode with its own tile load order (phase-2 loads in
+    phase 1, the own node's phase-3 loads before the second barrier), here
+    on partial tiles in x (830 = 12 x 64 + 62, 740 = 11 x 64 + 36) and y
+    (64 x 8 tiles in FP32, 64 x 4 in FP64): 2 steps against the oracle."""
+    wl = W.random_small(2, N, shape, seed=seed)
     o = oracle_run(wl, 2)
     g = gpu_run(wl, 2, precision)
-    e = _report("ragged 790x830 %s 2 steps" % precision, g, o)
+    e = _report("ragged %dx%d N=%d %s 2 steps" % (shape + (N, precision)),
+                g, o)
     fl = wl.psi >= 1e-2
     eP = rel_linf(g["P"][fl], o["P"][fl])
     print("P(psi>=1e-2) %.2e" % eP, flush=True)
