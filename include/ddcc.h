@@ -155,7 +155,8 @@ int ddcc_init_fields_dev(ddcc_ctx* ctx, const double* C_dev,
  * C_i from the pulled phase populations, one z-marching kernel for the
  * chemical potential mu_i, and one z-marching kernel for the node update.
  * Contexts whose step moves more than the 256 MB memory-side cache run the
- * same kernels with nontemporal stores (same results). */
+ * same kernels with nontemporal stores, and in 2D with the loads of a tile
+ * issued earlier (same results bit for bit). */
 int ddcc_step(ddcc_ctx* ctx, int64_t nsteps);
 
 /* C_i, u and P of the current time level (moment recovery of Section 3 and
