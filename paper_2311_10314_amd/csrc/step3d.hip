@@ -868,10 +868,13 @@ void k_step3d(Coef<double> kda, Coef<R> ka,
   // node's own inputs (NodeIn) for plane z + 1 are loaded at the end of the
   // node update of plane z, into the registers that plane z's inputs have
   // just freed, and plane z + 2 of the ring is fetched into registers before
-  // plane z is computed and put into LDS after it. The node update then
-  // waits only for the lagged-T gathers; before, each plane waited for its
-  // ring load (behind the previous plane's stores), its gathers and flow
-  // populations, then its phase populations. 169 -> 253 VGPRs, still two
+  // plane z is computed and put into LDS after it. The only loads the node
+  // update then issues are the lagged-T gathers (their wait also covers the
+  // previous plane's stores and the prefetched inputs, issued before them
+  // and by then overlapped with the ring put and the LDS gradients);
+  // before, each plane waited for its ring load (behind the previous
+  // plane's stores), its gathers and flow populations, then its phase
+  // populations. 169 -> 253 VGPRs, still two
   // waves per SIMD; 256^3 FP32 2.476 -> 2.352 ms per step (same box, bit for
   // bit the same results). Measured and left out: the node loads alone
   // (2.418 ms), also the T gathers one plane ahead (10 VGPRs spilled, 2.436
