@@ -7,6 +7,7 @@
   within 4 nodes, so the window's centre is exact). Samples: random nodes,
   nodes on the sphere's wall layer and on the droplet interface, nodes at
   the periodic boundary.
+* The same 3D box over 1000 steps: the FP32 context against the FP64 one.
 * The batched workload with all 256 instances (FP32, graph step loop, the
   autotuned tile as in the bench): the smallest instances against full
   oracle runs of the same steps.
@@ -105,3 +106,39 @@ def test_batched_full_workload_small_instances():
             i, wl.shape, ty, eC, eu, drift), flush=True)
         assert eC < 1e-5 and eu < 1e-5 and drift < 1e-6
     b.close()
+
+
+def test_sphere256_1000_steps_fp32_against_fp64():
+    """The 3D impact workload at its own size, 256^3, over 1000 steps: the
+    FP32 context (the bench's headline kernels) against the FP64 context,
+    which the oracle pins at 64^3 over 1000 steps to 1e-13 (the oracle
+    itself cannot run this box for 1000 steps here). Bars: C_i and u
+    1e-5, mass drift 1e-6 (FP32) and 1e-12 (FP64); P, formed as psi P /
+    psi, is compared where psi >= 1e-2 and held to 5e-5, which allows the
+    up to 100-fold amplification of the float32 rounding of psi P by the
+    division."""
+    from paper_2311_10314_amd.ddcc import Sim
+    wl = _sphere256()
+    out = {}
+    for prec in ("fp64", "fp32"):
+        sim = Sim.from_workload(wl, prec)
+        m0 = sim.mass()
+        sim.step(1000)
+        C, u, P = sim.read_moments()
+        m1 = sim.mass()
+        sim.close()
+        drift = float(np.max(np.abs(m1 - m0) / np.abs(m0)))
+        print("%s: mass drift %.2e" % (prec, drift), flush=True)
+        assert drift < (1e-12 if prec == "fp64" else 1e-6)
+        out[prec] = (C, u, P)
+    (C64, u64, P64), (C32, u32, P32) = out["fp64"], out["fp32"]
+    eC = max(rel_linf(C32[i], C64[i]) for i in range(len(C64)))
+    eu = rel_linf(u32, u64)
+    psi = np.asarray(wl.psi)
+    fl = psi >= 1e-2
+    eP = rel_linf(P32[fl], P64[fl])
+    k = np.unravel_index(np.argmax(np.where(fl, np.abs(P32 - P64), 0.0)),
+                         P64.shape)
+    print("256^3 1000 steps FP32 vs FP64: C %.2e u %.2e P(psi>=1e-2) %.2e "
+          "(largest at psi = %.3g)" % (eC, eu, eP, psi[k]), flush=True)
+    assert eC < 1e-5 and eu < 1e-5 and eP < 5e-5
