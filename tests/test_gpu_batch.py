@@ -211,3 +211,34 @@ def test_batch_parameters_must_match_the_batch():
         b.set_params(1, bad)
     assert e.value.code == DDCC_E_INVAL
     b.close()
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 1e-5)])
+def test_full_batched_workload_2000_steps(precision, tol):
+    """The whole 256-instance workload over its 2000 steps (graph step
+    loop; streaming step mode), two of its smallest instances against
+    oracle runs of the same length: C_i and u within the bar, P where
+    psi >= 1e-2, mass drift 1e-12 (FP64) and 1e-6 (FP32)."""
+    from paper_2311_10314_amd.ddcc import Batch
+    steps = 2000
+    wls = W.batched_instances(256)
+    pick = sorted(range(256), key=lambda i: wls[i].nodes)[:2]
+    refs = {i: oracle_run(wls[i], steps) for i in pick}
+    b = Batch.from_workloads(wls, precision)
+    b.set_graph(50)
+    m0 = {i: b.mass(i) for i in pick}
+    b.step(steps)
+    for i in pick:
+        C, u, P = b.read_moments(i)
+        o = refs[i]
+        fl = wls[i].psi >= 1e-2
+        eC = max(rel_linf(C[j], o["C"][j]) for j in range(len(C)))
+        eu = rel_linf(u, o["u"])
+        eP = rel_linf(P[fl], o["P"][fl])
+        drift = float(np.max(np.abs(b.mass(i) - m0[i]) / np.abs(m0[i])))
+        print("%s instance %d %s after %d: C %.2e u %.2e P %.2e drift %.2e"
+              % (precision, i, wls[i].shape, steps, eC, eu, eP, drift),
+              flush=True)
+        assert eC < tol and eu < tol and eP < tol
+        assert drift < (1e-12 if precision == "fp64" else 1e-6)
+    b.close()
