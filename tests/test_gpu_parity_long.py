@@ -13,6 +13,9 @@ compared where psi >= 1e-2 (inside solids it is round-off divided by a
 vanishing psi) and phi P everywhere.
 
 Measured (one MI355X): FP32 porous u 8.5e-7, 3D u 6.6e-6, C 1.1e-7.
+
+The porous box over its full 20000 steps is checked FP32 against FP64
+(the FP64 context is the one the stored run pins).
 """
 import os
 
@@ -66,3 +69,34 @@ def test_1000_steps_against_stored_oracle_run(name, precision):
     for k, v in e.items():
         assert v < EXCEPTIONS.get((name, precision, k), tol), (k, e)
     assert drift < dtol
+
+
+def test_porous512_20000_steps_fp32_against_fp64():
+    """The porous 512 x 512 N = 3 box over its full 20000 steps (the oracle
+    would take about an hour here): the FP32 context against the FP64
+    context, which the stored oracle run pins over the first 1000 steps.
+    Bars: C_i and u 1e-5, mass drift 1e-6 (FP32) and 1e-12 (FP64); P where
+    psi >= 1e-2, held to 5e-5 for the up to 100-fold amplification of the
+    float32 rounding of psi P by the division by psi."""
+    from paper_2311_10314_amd.ddcc import Sim
+    wl = W.porous_bands_2d(n=512)
+    out = {}
+    for prec in ("fp64", "fp32"):
+        sim = Sim.from_workload(wl, prec)
+        m0 = sim.mass()
+        sim.step(20000)
+        C, u, P = sim.read_moments()
+        m1 = sim.mass()
+        sim.close()
+        drift = float(np.max(np.abs(m1 - m0) / np.abs(m0)))
+        print("%s: mass drift %.2e" % (prec, drift), flush=True)
+        assert drift < (1e-12 if prec == "fp64" else 1e-6)
+        out[prec] = (C, u, P)
+    (C64, u64, P64), (C32, u32, P32) = out["fp64"], out["fp32"]
+    fl = np.asarray(wl.psi) >= 1e-2
+    eC = max(rel_linf(C32[i], C64[i]) for i in range(len(C64)))
+    eu = rel_linf(u32, u64)
+    eP = rel_linf(P32[fl], P64[fl])
+    print("porous 512^2 20000 steps FP32 vs FP64: C %.2e u %.2e "
+          "P(psi>=1e-2) %.2e" % (eC, eu, eP), flush=True)
+    assert eC < 1e-5 and eu < 1e-5 and eP < 5e-5
