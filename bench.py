@@ -48,6 +48,9 @@ KERNEL_SOURCES = {
            "paper_2311_10314_amd/csrc/lattice.hpp",
            "paper_2311_10314_amd/csrc/coef.hpp"],
 }
+# the 2D porous box at an HBM size (2048^2) runs the same sources
+KERNEL_SOURCES["2dhbm"] = KERNEL_SOURCES["2d"]
+HBM_2D_N = 2048
 # element bytes (populations, fields) per precision
 PREC_BYTES = {"fp64": (8, 8), "fp32": (4, 4), "fp16": (2, 4), "bf16": (2, 4)}
 # The kernels of one step, as rocprofv3 names them (the 3D step is three
@@ -67,6 +70,8 @@ KERNEL_TAGS = {   # the 256^3 steps run in the streaming mode (3), 512^2 in 0
                      "k_step3dILi2ENS_5D3Q15ENS_5D3Q19EDF16_ffLi3ELi4E"],
     ("2d", "fp32"): ["k_step2d<3, float, float, float, 0, 8>"],
     ("2d", "fp64"): ["k_step2d<3, double, double, double, 0, 4>"],
+    ("2dhbm", "fp32"): ["k_step2d<3, float, float, float, 3, 8>"],
+    ("2dhbm", "fp64"): ["k_step2d<3, double, double, double, 3, 4>"],
 }
 HEAD_N = 256          # the 3D box of the headline
 REDUCED_N = 48        # the same generator at 48^3 for the oracle legs
@@ -592,6 +597,9 @@ def traffic_summary(fetch_dir, write_dir, kind, precision):
     if kind == "3d":
         wl = W.droplet_impact_sphere_3d(n=HEAD_N)
         geom = (2, 3, 15, 19)
+    elif kind == "2dhbm":
+        wl = W.porous_bands_2d(n=HBM_2D_N)
+        geom = (3, 2, 9, 9)
     else:
         wl = W.porous_bands_2d(n=512)
         geom = (3, 2, 9, 9)
@@ -660,7 +668,7 @@ def main():
     ap.add_argument("--precisions", default="fp32,fp64,fp16,bf16",
                     help="3D precisions to time (the first is not repeated)")
     ap.add_argument("--no-2d", action="store_true")
-    ap.add_argument("--porous-hbm", type=int, default=2048,
+    ap.add_argument("--porous-hbm", type=int, default=HBM_2D_N,
                     help="side of the 2D porous box timed at an HBM size "
                          "(0: skip)")
     ap.add_argument("--porous-hbm-steps", type=int, default=200)
@@ -760,16 +768,14 @@ def main():
                                   "D2Q9, rho 1:10:100" % (n3, n3),
                       "note": "streams from HBM (the library's streaming "
                               "step mode); the same kernels as the 1024^2 "
-                              "and 790x830 streaming parity tests; no "
-                              "counter run for this box (traffic null)"}
+                              "and 790x830 streaming parity tests; traffic "
+                              "from the counter run of the 2048^2 box"}
         for prec in ("fp32", "fp64"):
             s3, ms3, dr3 = time_gpu(wl3, prec, a.porous_hbm_steps, 10, torch)
             s3.close()
-            r = roofline("2d", prec, wl3.nodes, ms3, 3, 2, 9, 9, torch)
-            r["traffic"] = None
-            r["kernels"] = ["k_step2d<3, float, float, float, 3, 8>"
-                            if prec == "fp32" else
-                            "k_step2d<3, double, double, double, 3, 4>"]
+            r = roofline("2dhbm", prec, wl3.nodes, ms3, 3, 2, 9, 9, torch)
+            if n3 != HBM_2D_N:  # counters were taken on the 2048^2 box
+                r["traffic"] = None
             porous_hbm[prec] = {"value": wl3.nodes / (ms3 * 1e-3) / 1e6,
                                 "unit": "MLUPS", "ms_per_step": ms3,
                                 "steps": a.porous_hbm_steps,
