@@ -681,7 +681,7 @@ def main():
                     metavar=("FETCH_DIR", "WRITE_DIR", "KIND", "PRECISION"),
                     help="write profiles/hbm_traffic.json from two "
                          "rocprofv3 counter runs (no GPU needed); KIND is "
-                         "3d or 2d")
+                         "3d, 2d or 2dhbm")
     a = ap.parse_args()
     if a.traffic_summary:
         traffic_summary(*a.traffic_summary)
