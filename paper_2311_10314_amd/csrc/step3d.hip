@@ -874,9 +874,9 @@ void k_step3d(Coef<double> kda, Coef<R> ka,
   // and by then overlapped with the ring put and the LDS gradients);
   // before, each plane waited for its ring load (behind the previous
   // plane's stores), its gathers and flow populations, then its phase
-  // populations. 169 -> 253 VGPRs, still two
-  // waves per SIMD; 256^3 FP32 2.476 -> 2.352 ms per step (same box, bit for
-  // bit the same results). Measured and left out: the node loads alone
+  // populations. 169 -> 253 VGPRs, still two waves per SIMD; 256^3 FP32
+  // 2.476 -> 2.352 ms per step (same box, bit for bit the same results).
+  // Measured and left out: the node loads alone
   // (2.418 ms), also the T gathers one plane ahead (10 VGPRs spilled, 2.436
   // ms), and the pipeline for the 16-bit storages, whose node update at 161
   // to 165 VGPRs runs three waves per SIMD and drops to two with it (FP16
