@@ -329,7 +329,7 @@ struct Step2D {
     // the collision (phase 3 would otherwise load them again, after the
     // whole chunk's phase-1 traffic has gone through L2). In float64 that
     // takes the kernel to 187 VGPRs and two waves per SIMD, and is still
-    // faster (same box, 512^2 N = 3: 48.3 -> 42.4 us; 2048^2: 825 -> 815 us).
+    // faster (same GPU, 512^2 N = 3: 48.3 -> 42.4 us; 2048^2: 825 -> 815 us).
     constexpr bool KEEP = MODE == MODE_STEP || MODE == MODE_STREAM;
     Keep fown;
     node1<KEEP>(sm, kd, b, kd, x0, y0, tx + 2, ty + 2, psiC, &fown);
@@ -358,7 +358,7 @@ struct Step2D {
   // loads go out in phase 1 (T straight into LDS, E_i into registers) and
   // the own node's phase-3 loads before the second barrier, so a tile waits
   // on memory once in phase 1 and once, overlapped by the barrier and the
-  // LDS gradients, in phase 3. Same box, same results bit for bit, ms per
+  // LDS gradients, in phase 3. Same GPU, same results bit for bit, ms per
   // step: porous 2048^2 N = 3 FP32 0.389 -> 0.377, FP64 0.758 -> 0.709;
   // disk 2048^2 N = 2 FP32 0.283 -> 0.265, FP64 0.499 -> 0.496; disk 4096^2
   // FP32 1.136 -> 1.080, FP64 2.130 -> 2.158; 256 batched instances 0.400
@@ -426,7 +426,7 @@ struct Step2D {
     const int tx = tid % TX, ty = tid / TX;
     D psiC[N], psimu_d[N], dummy[N];
     // pulled populations kept in registers as in run() (float64, 256
-    // instances, 64 x 8 tiles: 0.829 -> 0.756 ms per step, same box)
+    // instances, 64 x 8 tiles: 0.829 -> 0.756 ms per step, same GPU)
     constexpr bool KEEP = MODE == MODE_STEP || MODE == MODE_STREAM;
     Keep fown;
     node1<KEEP>(sm, kd, b, gd, x0, y0, tx + 2, ty + 2, psiC, &fown);
@@ -717,7 +717,7 @@ struct Step2D {
 // kd, k: the context's coefficients in device memory. Passed by value the
 // two structs (about 1.5 KB) overflow the scalar registers and spill into
 // VGPR lanes; read through __restrict__ pointers they are scalar loads where
-// used (512^2 N = 3, same box: FP32 23.3 -> 22.4 us, FP64 49.2 -> 48.3 us).
+// used (512^2 N = 3, same GPU: FP32 23.3 -> 22.4 us, FP64 49.2 -> 48.3 us).
 template <int N, class Pop, class S, class R, int MODE, int TY>
 __global__ __launch_bounds__(TX* TY) void k_step2d(
     const Coef<double>* __restrict__ kd, const Coef<R>* __restrict__ k,

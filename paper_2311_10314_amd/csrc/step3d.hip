@@ -38,7 +38,7 @@
 // are evaluated in float64 in every precision; k_mu3d computes the chemical
 // potential in the field type (float32 in float contexts, whose C and psi
 // fields it reads are float32 already; 256^3 FP32 2.51 -> 2.47 ms per step,
-// FP16 1.70 -> 1.67 ms, same box, the 1000-step errors unchanged).
+// FP16 1.70 -> 1.67 ms, same GPU, the 1000-step errors unchanged).
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
@@ -245,11 +245,11 @@ __global__ __launch_bounds__(TX* TY) void k_frac3d(Coef<double> k,
 // neighbour (the 19-point stencil otherwise issues 19 loads per node and
 // field through L2). The ring holds the fields in their storage type (float32 in float
 // contexts; 256^3 FP32: 196 -> 185 us per launch against a float64 ring,
-// same box). The step kernel's ring stays float64: typed as the fields it
+// same GPU). The step kernel's ring stays float64: typed as the fields it
 // took more registers and was slower (FP32 2.69 -> 2.73 ms, FP16 1.89 ->
 // 2.81 ms per step).
 // Planes per workgroup: each column reloads two halo planes, but more
-// columns run at once (same box, 256^3 per step, 16 -> 8 planes: FP32 2.86 ->
+// columns run at once (same GPU, 256^3 per step, 16 -> 8 planes: FP32 2.86 ->
 // 2.80 ms, FP16 and BF16 0.5 % faster, FP64 unchanged; 4 planes: FP32 2.78
 // ms, the others 1 % slower than at 16; 32 planes slower for all).
 constexpr int ZB = 8;
@@ -297,7 +297,7 @@ __global__ __launch_bounds__(TX* TY) void k_mu3d(Coef<double> k, Bufs<Pop, S> b)
 
   // Plane z + 2 is fetched into registers before plane z is computed and
   // put into the ring after it, so its load latency overlaps that work
-  // (256^3 FP32: 184 -> 163 us per launch, same box).
+  // (256^3 FP32: 184 -> 163 us per launch, same GPU).
   constexpr int PER = (HN + TX * TY - 1) / (TX * TY);  // ring slots per thread
   S pre[PER][N + 1];
   auto fetch = [&](int zz) {
@@ -347,7 +347,7 @@ __global__ __launch_bounds__(TX* TY) void k_mu3d(Coef<double> k, Bufs<Pop, S> b)
       const D psi = pz[1]->p[ly][lx];
       const D psih = psi > D(k.psi_min) ? psi : D(k.psi_min);
       // one division for the N phases (the kernel is VALU-bound: 161 ->
-      // 157 us per launch at 256^3 FP32, same box)
+      // 157 us per launch at 256^3 FP32, same GPU)
       const D ipsih = D(1) / psih;
       D C[N], L[N];
       // div(psi grad C_j): the face and the edge terms summed apart and
@@ -801,7 +801,7 @@ __device__ inline void step3d_node(const Coef<double>& kd, const Coef<R>& k,
 // Left to itself the compiler gives the float64 kernel 256+ registers and
 // one wave per SIMD. The float kernels were capped at three while their
 // coefficients came as arguments (at two, FP32 was 17 % slower); with the
-// coefficient table two is the faster cap (same box, 256^3 per step: FP32
+// coefficient table two is the faster cap (same GPU, 256^3 per step: FP32
 // 2.95 -> 2.86 ms, FP16 2.68 -> 1.98 ms, BF16 unchanged).
 template <int N, int TY>
 constexpr int step3d_waves() {
@@ -821,7 +821,7 @@ void k_step3d(Coef<double> kda, Coef<R> ka,
   // Coefficients as kernel arguments overflow the scalar registers and spill
   // into VGPR lanes; read from a device table they cost no spills but scalar
   // loads inside the z loop. Which is faster depends on the storage type
-  // (same box, 256^3: table for BF16 2.79 -> 2.00 ms, FP32 3.00 -> 2.97 ms
+  // (same GPU, 256^3: table for BF16 2.79 -> 2.00 ms, FP32 3.00 -> 2.97 ms
   // and FP16 2.68 -> 1.98 ms per step, the last two at two waves per SIMD;
   // arguments for FP64 5.09 vs 5.60 ms).
   constexpr bool TABLE = std::is_same_v<Pop, __bf16> ||
@@ -875,7 +875,7 @@ void k_step3d(Coef<double> kda, Coef<R> ka,
   // before, each plane waited for its ring load (behind the previous
   // plane's stores), its gathers and flow populations, then its phase
   // populations. 169 -> 253 VGPRs, still two waves per SIMD; 256^3 FP32
-  // 2.476 -> 2.352 ms per step (same box, bit for bit the same results).
+  // 2.476 -> 2.352 ms per step (same GPU, bit for bit the same results).
   // Measured and left out: the node loads alone
   // (2.418 ms), also the T gathers one plane ahead (10 VGPRs spilled, 2.436
   // ms), and the pipeline for the 16-bit storages, whose node update at 161
